@@ -1,0 +1,194 @@
+/*
+ * hgf.h -- C ABI of the MI355X (gfx950) hardware-efficient guided filter (HGF)
+ * for multi-label cost volumes.
+ *
+ * Problem (paper: Dai et al., "Hardware-Efficient Guided Image Filtering For
+ * Multi-Label Problem", arXiv 1803.00005):
+ *   a multi-label system stores the cost of label l at pixel (x, y) in a cost
+ *   volume V(x, y, l), filters every label slice under a guidance image and
+ *   picks the winner-takes-all label per pixel (Sec. 1).  Each slice Y is
+ *   filtered by HGF (Sec. 4): an n-channel polynomial guidance G is
+ *   synthesized from the input guidance I (Sec. 4.2), a ridge regression is
+ *   fitted in every (2r+1)x(2r+1) window (Eq. 6 / Eq. 2) with the per-pixel
+ *   matrix inverted by the recursion of Prop. 1, and the window predictions
+ *   are averaged (Eq. 7, Eq. 11).
+ *
+ * Conventions shared by every call
+ *   - Device pointers are plain HIP device addresses (e.g. the data_ptr() of
+ *     a torch CUDA tensor).  The caller owns every buffer it passes in;
+ *     the library owns hgf_context and hgf_guide objects.
+ *   - Layouts (row-major, no padding unless a leading dimension is given):
+ *       guide  float32 [m][H][W]           planar channels
+ *       cost   float32 or bfloat16 [H][W][ld]   pixel-major, labels contiguous
+ *       out    float32 [H][W][ld]          filtered costs Z
+ *       labels int32   [H][W]              winner-takes-all label
+ *   - Windows are clipped at the image border: the box filter sums the
+ *     in-image pixels of the window and the average divides by their count
+ *     (the average operator A(X) = B(X) / B(1) of Sec. 4.3).
+ *   - All calls are asynchronous on the given hipStream_t (NULL = the null
+ *     stream).  Argument errors are detected on the host before anything is
+ *     enqueued; launch errors are returned at once; faults inside kernels
+ *     surface at the caller's next synchronisation.
+ *   - Every call returns an hgf_status; no C++ exception crosses the ABI.
+ *     hgf_last_error() returns a thread-local detail string.
+ *   - A context must not be used from two host threads at once.
+ *   - Results are deterministic: for fixed parameters they do not depend on
+ *     the stream, on other images in a batch, or on label chunking.
+ */
+#ifndef HGF_H
+#define HGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HGF_OK = 0,
+  HGF_E_INVALID = -1,     /* an argument is out of range or inconsistent */
+  HGF_E_NOMEM = -2,       /* a device allocation failed or would exceed the budget */
+  HGF_E_DEVICE = -3,      /* a HIP runtime call or kernel launch failed */
+  HGF_E_UNSUPPORTED = -4, /* valid but not compiled in (n, radius, dtype) */
+  HGF_E_BUSY = -5         /* the serving queue is full */
+} hgf_status;
+
+typedef enum { HGF_F32 = 0, HGF_BF16 = 1 } hgf_dtype;
+
+/* Polynomial guidance basis (Sec. 4.2).
+ *   MONOMIAL: every monomial of total degree 1..d of the m channels, graded
+ *             lexicographic with channel 1 first (RGB, d=2: R,G,B,R^2,RG,RB,
+ *             G^2,GB,B^2); n = C(m+d, d) - 1.
+ *   POWER:    the paper's map G_{(i-1)d+j} = I_i^j, channel-major; n = m d. */
+typedef enum { HGF_BASIS_MONOMIAL = 0, HGF_BASIS_POWER = 1 } hgf_basis;
+
+/* Regularisation.
+ *   COVARIANCE: the guided-filter form of Sec. 5.1 (Eqs. 12-13): intercept
+ *               free, (Sigma_p + eps E) a_p = cov_p(G, Y) on window means.
+ *   RIDGE:      the paper's HGF definition, Eq. 6: every coefficient,
+ *               intercept included, penalised by lambda on raw window sums,
+ *               (lambda E + X^T X) w_p = X^T Y (Eq. 2). */
+typedef enum { HGF_REG_COVARIANCE = 0, HGF_REG_RIDGE = 1 } hgf_reg;
+
+typedef struct {
+  int32_t height;          /* H >= 1 */
+  int32_t width;           /* W >= 1 */
+  int32_t guide_channels;  /* m in {1, 2, 3} */
+  int32_t degree;          /* d >= 1 */
+  int32_t basis;           /* hgf_basis */
+  int32_t reg;             /* hgf_reg */
+  int32_t radius;          /* r >= 0: window side 2r + 1 */
+  int32_t num_labels;      /* L >= 1 */
+  double eps;              /* > 0: eps (COVARIANCE) or lambda (RIDGE) */
+  int32_t cost_dtype;      /* hgf_dtype of the cost volume */
+  int32_t cost_ld;         /* label stride of cost (0 = num_labels) */
+  int32_t out_ld;          /* label stride of out  (0 = num_labels) */
+  int32_t reserved;        /* must be 0 */
+} hgf_params;
+
+typedef struct hgf_context hgf_context;
+typedef struct hgf_guide hgf_guide;
+
+/* n, the number of guidance channels the basis synthesizes from m channels
+ * at degree d (Sec. 4.2), or -1 if m, d or basis is invalid. Host only. */
+int32_t hgf_num_channels(int32_t m, int32_t d, int32_t basis);
+
+/* 1 if (n, radius) has compiled kernels for the given regularisation, else 0. Host only. */
+int32_t hgf_is_supported(int32_t n, int32_t radius, int32_t reg);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * device memory the context allocates for itself (0 = no bound).  Allocates
+ * nothing on the device until a call needs library-owned memory. */
+hgf_status hgf_create(int32_t device, size_t hbm_budget_bytes, hgf_context** out);
+void hgf_destroy(hgf_context* ctx);
+
+/* Bytes of device workspace hgf_filter needs for these parameters, with the
+ * label chunks it processes per launch.  Host only; validates params. */
+hgf_status hgf_workspace_size(const hgf_params* params, size_t* bytes);
+
+/* The whole hot path on one image (Fig. 2 of the paper for every slice):
+ * guidance synthesis, guidance box statistics, per-pixel inverse (Prop. 1),
+ * per-label coefficient box sums and solve (Eq. 5 / Eq. 13), coefficient
+ * box filter and output (Eq. 11), winner-takes-all (Sec. 1).
+ *   guide      device float32 [m][H][W]
+ *   cost       device [H][W][cost_ld] of cost_dtype; labels 0..L-1 used
+ *   out        device float32 [H][W][out_ld] or NULL (labels only)
+ *   labels     device int32 [H][W] or NULL (no winner-takes-all)
+ *   workspace  device buffer of at least hgf_workspace_size() bytes, 256-byte
+ *              aligned, or NULL to use context-owned memory
+ * Errors: HGF_E_INVALID (bad params, both outputs NULL, small workspace),
+ * HGF_E_UNSUPPORTED (n or radius not compiled in), HGF_E_NOMEM, HGF_E_DEVICE. */
+hgf_status hgf_filter(hgf_context* ctx, const hgf_params* params,
+                      const float* guide, const void* cost,
+                      float* out, int32_t* labels,
+                      void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Two-phase form.  hgf_guide_create computes the guidance part once and keeps
+ * it resident on the device (the all-pair box filters of the guidance are
+ * computed once and shared by every slice, Sec. 5.3): the synthesized
+ * guidance, the window means and the per-pixel inverses.  The guide buffer
+ * is read during the call only.  params->num_labels is the total label count
+ * of the volume that later chunks belong to. */
+hgf_status hgf_guide_create(hgf_context* ctx, const hgf_params* params,
+                            const float* guide, void* hip_stream, hgf_guide** out);
+
+/* Filter labels [label_begin, label_begin + label_count) with resident
+ * guidance statistics.
+ *   cost_chunk  device [H][W][ld] of the params' cost dtype, label_begin at column 0
+ *   out_chunk   device float32 [H][W][ld] or NULL
+ *   best_cost, labels  device float32 / int32 [H][W] running minimum and
+ *               argmin over the labels filtered so far; when label_begin == 0
+ *               they are (re)initialised, otherwise merged (lower cost wins,
+ *               lower label on ties).  Both NULL: no winner-takes-all.
+ *   ld          label stride of cost_chunk and out_chunk (0 = label_count). */
+hgf_status hgf_guide_filter(hgf_context* ctx, hgf_guide* guide,
+                            const void* cost_chunk, int32_t label_begin,
+                            int32_t label_count, int32_t ld, float* out_chunk,
+                            float* best_cost, int32_t* labels, void* hip_stream);
+
+/* Device bytes held by a resident guide. */
+size_t hgf_guide_bytes(const hgf_guide* guide);
+void hgf_guide_destroy(hgf_guide* guide);
+
+/* Copy a resident guide's per-pixel statistics out (for inspection):
+ *   mu    device float64 [H][W][n]   window means of the (shifted) guidance
+ *   minv  device float64 [H][W][D(D+1)/2] packed upper triangle of the
+ *         per-pixel inverse, row by row (D = n covariance, n + 1 ridge)
+ *   shift device float64 [n] the constant subtracted from each guidance
+ *         channel (0 in ridge mode)
+ * Any pointer may be NULL. */
+hgf_status hgf_guide_export(const hgf_guide* guide, double* mu, double* minv,
+                            double* shift, void* hip_stream);
+
+/* Filter `count` images of uneven size and label count (the batched form):
+ * every image runs through the same stages, each stage one launch over a
+ * work list spanning all images, the sequence captured once in a hipGraph
+ * per batch shape and replayed.  Arrays of length count. */
+hgf_status hgf_filter_batch(hgf_context* ctx, int32_t count, const hgf_params* params,
+                            const float* const* guides, const void* const* costs,
+                            float* const* outs, int32_t* const* labels,
+                            void* hip_stream);
+
+/* Standalone clipped box sum (Prop. 2) of C float32 images [C][H][W]:
+ * out[c][y][x] = sum of in[c] over the clipped (2r+1)^2 window.  in and out
+ * must not overlap. */
+hgf_status hgf_box_sum(const float* in, float* out, int32_t channels,
+                       int32_t height, int32_t width, int32_t radius,
+                       void* hip_stream);
+
+/* Batched inverse of `count` symmetric positive definite D x D matrices by
+ * the branch-free recursion of Prop. 1 (Sherman-Morrison bordering, no
+ * pivoting), in float64.  a: device [count][D][D] (only the upper triangle
+ * is read); minv: device [count][D][D] (full symmetric result). 1 <= D <= 20. */
+hgf_status hgf_spd_inverse(const double* a, double* minv, int32_t dim,
+                           int32_t count, void* hip_stream);
+
+const char* hgf_status_string(hgf_status status);
+const char* hgf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGF_H */

@@ -1,0 +1,7 @@
+// Coefficient kernels for n = 1 guidance channels (all compiled radii, both
+// regularisation forms, float32 and bfloat16 cost).
+#include "coef.hpp"
+
+namespace hgf {
+hipError_t launch_coef_n1(const CoefLaunch& a, hipStream_t s) { return coef_launch_n<1>(a, s); }
+}  // namespace hgf

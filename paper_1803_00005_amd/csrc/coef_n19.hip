@@ -1,0 +1,7 @@
+// Coefficient kernels for n = 19 guidance channels (all compiled radii, both
+// regularisation forms, float32 and bfloat16 cost).
+#include "coef.hpp"
+
+namespace hgf {
+hipError_t launch_coef_n19(const CoefLaunch& a, hipStream_t s) { return coef_launch_n<19>(a, s); }
+}  // namespace hgf

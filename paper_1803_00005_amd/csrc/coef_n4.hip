@@ -1,0 +1,7 @@
+// Coefficient kernels for n = 4 guidance channels (all compiled radii, both
+// regularisation forms, float32 and bfloat16 cost).
+#include "coef.hpp"
+
+namespace hgf {
+hipError_t launch_coef_n4(const CoefLaunch& a, hipStream_t s) { return coef_launch_n<4>(a, s); }
+}  // namespace hgf

@@ -1,0 +1,426 @@
+// Guidance part of the filter, run once per image and shared by every label
+// slice (the all-pair guidance box filters are computed once, Sec. 5.3):
+//   a1  polynomial guidance synthesis (Sec. 4.2),
+//   a2  window sums of G_i and G_i G_j (Prop. 2),
+//   a3  per-pixel inverse of the regularised window system by the recursion
+//       of Prop. 1 (bordering form, branch-free: every Schur complement is
+//       at least the regulariser, so no pivot is ever needed).
+#include "hgf_launch.hpp"
+
+namespace hgf {
+namespace {
+
+__device__ __forceinline__ double monomial(const MonoTable& t, int k, const float* iv) {
+  double v = 1.0;
+  for (int c = 0; c < t.m; ++c) {
+    const double x = static_cast<double>(iv[c]);
+    for (int e = 0; e < t.e[k][c]; ++e) v *= x;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// a1: channel means (deterministic two-stage reduction) and the synthesized
+// guidance.  Each block reduces a fixed pixel subset in a fixed order, so the
+// result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void guide_mean_partial_kernel(
+    const float* __restrict__ I, int P, MonoTable t, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double acc[kMaxD];
+#pragma unroll
+  for (int k = 0; k < kMaxD; ++k) acc[k] = 0.0;
+  for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256) {
+    float iv[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < t.m; ++c) iv[c] = I[static_cast<size_t>(c) * P + p];
+#pragma unroll
+    for (int k = 0; k < kMaxD; ++k)
+      if (k < t.n) acc[k] += monomial(t, k, iv);
+  }
+  for (int k = 0; k < t.n; ++k) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxD; ++q)
+      if (q == k) v = acc[q];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x * kMaxD + k] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void guide_mean_final_kernel(const double* __restrict__ partial, int nblocks, int n,
+                                        int P, int centre, double* __restrict__ shift) {
+  const int k = threadIdx.x;
+  if (k >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[b * kMaxD + k];
+  shift[k] = centre ? s / static_cast<double>(P) : 0.0;
+}
+
+// g32 holds n + 1 channels per pixel, channel 0 being the constant G_0 = 1, so
+// the per-label kernels index the multiplier of every box channel uniformly.
+__global__ __launch_bounds__(256) void guide_synth_kernel(
+    const float* __restrict__ I, int P, MonoTable t, const double* __restrict__ shift,
+    float* __restrict__ g32, double* __restrict__ g64) {
+  const int n1 = t.n + 1;
+  const size_t idx = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  const size_t total = static_cast<size_t>(P) * n1;
+  if (idx >= total) return;
+  const int p = static_cast<int>(idx / n1);
+  const int k = static_cast<int>(idx - static_cast<size_t>(p) * n1);
+  if (k == 0) {
+    g32[idx] = 1.0f;
+    return;
+  }
+  float iv[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < t.m; ++c) iv[c] = I[static_cast<size_t>(c) * P + p];
+  const double g = monomial(t, k - 1, iv) - shift[k - 1];
+  g64[static_cast<size_t>(p) * t.n + (k - 1)] = g;
+  g32[idx] = static_cast<float>(g);
+}
+
+// ---------------------------------------------------------------------------
+// a2: window sums of the K = n + n(n+1)/2 guidance moments.  Lanes are moment
+// channels; a wave walks down a band of rows over a strip of 64 state
+// columns, keeping float64 vertical running sums in registers (add the row
+// entering the window, subtract the row leaving it) and forming the
+// horizontal window sums in registers, so no cross-lane traffic is needed.
+// Output S[p][k], coalesced over k.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(256) void moments_kernel(
+    const double* __restrict__ g64, int n, int K, int H, int W, int band_h, int strips,
+    double* __restrict__ S) {
+  constexpr int SOUT = kStrip - 2 * R;
+  const int lane = threadIdx.x & 63;
+  const int k = static_cast<int>(blockIdx.y) * 256 + threadIdx.x;
+  (void)lane;
+  const bool kok = k < K;
+  int ci = 0, cj = -1;
+  if (kok) {
+    if (k < n) {
+      ci = k;
+    } else {
+      int q = k - n, i = 0;
+      while (q >= n - i) { q -= n - i; ++i; }
+      ci = i;
+      cj = i + q;
+    }
+  }
+  const int strip = static_cast<int>(blockIdx.x) % strips;
+  const int band = static_cast<int>(blockIdx.x) / strips;
+  const int x_out0 = strip * SOUT;
+  const int xs = x_out0 - R;
+  const int y0 = band * band_h;
+  const int y1 = min(H, y0 + band_h);
+
+  double vs[kStrip];
+#pragma unroll
+  for (int c = 0; c < kStrip; ++c) vs[c] = 0.0;
+
+  // lanes past the last moment channel read channel 0 and never store
+  const int cic = kok ? ci : 0;
+  const int cjc = (kok && cj >= 0) ? cj : 0;
+  const double jone = (kok && cj >= 0) ? 0.0 : 1.0;
+
+  // Branch-free vertical update: columns outside the image read a clamped
+  // pixel with weight 0; the strip origin is laundered so per-column offsets
+  // are not hoisted out of the row loop.
+  auto acc_row = [&](int yy, double sgn) {
+    int xsl = xs;
+    asm volatile("" : "+s"(xsl));
+    const size_t rowp = static_cast<size_t>(yy) * W;
+#pragma unroll
+    for (int c = 0; c < kStrip; ++c) {
+      if ((c & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+      const int xr = xsl + c;
+      const int xc = min(max(xr, 0), W - 1);
+      const size_t p = rowp + xc;
+      const double gi = g64[p * n + cic];
+      const double gj = fma(g64[p * n + cjc], 1.0 - jone, jone);
+      vs[c] = fma((xr == xc) ? sgn * gi : 0.0, gj, vs[c]);
+    }
+  };
+
+  for (int yy = max(0, y0 - R); yy <= min(H - 1, y0 + R); ++yy) acc_row(yy, 1.0);
+  for (int y = y0; y < y1; ++y) {
+    if (y > y0) {
+      if (y + R < H) acc_row(y + R, 1.0);
+      if (y - R - 1 >= 0) acc_row(y - R - 1, -1.0);
+    }
+    double hs = 0.0;
+#pragma unroll
+    for (int c = 0; c <= 2 * R; ++c) hs += vs[c];
+#pragma unroll
+    for (int j = 0; j < SOUT; ++j) {
+      if (j > 0) hs += vs[j + 2 * R] - vs[j - 1];
+      const int x = x_out0 + j;
+      if (x < W && kok) S[(static_cast<size_t>(y) * W + x) * K + k] = hs;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a3: per-pixel inverse of the D x D window system by bordering, float64.
+//
+// Prop. 1 builds (lambda E + sum_i c_i c_i^T)^-1 = lambda^-1 E + sum alpha_ij c_i c_j^T
+// by adding one channel kappa at a time (Sherman-Morrison); its alpha equals
+// -lambda^-1 (lambda E + K)^-1 with K the Gram matrix of the channels added
+// so far.  Written for M = -lambda alpha = (lambda E + K)^-1 the same
+// recursion reads, with g = K[0:kappa, kappa] and u = M g:
+//   s = lambda + K_kk - g^T u   (Schur complement; >= lambda, no pivoting)
+//   M <- [[M + u u^T / s, -u / s], [-u^T / s, 1 / s]]
+// which is the paper's update scaled by -lambda (gamma = -lambda / s,
+// beta = -u / lambda).  Covariance form: K -> window covariance Sigma_p,
+// lambda -> eps (Sec. 5.1 applies the same inverse to Eq. 13).  Ridge form:
+// K -> raw window sums of [1, G][1, G]^T, lambda as given (Eq. 6).
+// ---------------------------------------------------------------------------
+template <int D, int RIDGE>
+__global__ __launch_bounds__(64) void invert_kernel(
+    const double* __restrict__ S, int H, int W, int R, double eps,
+    double* __restrict__ mu_out, double* __restrict__ minv_out) {
+  constexpr int NG = RIDGE ? D - 1 : D;             // guidance channels n
+  constexpr int K = NG + NG * (NG + 1) / 2;
+  constexpr int PD = D * (D + 1) / 2;
+  const int p = static_cast<int>(blockIdx.x) * 64 + threadIdx.x;
+  if (p >= H * W) return;
+  const int y = p / W;
+  const int x = p - y * W;
+  const double Np = static_cast<double>(window_count(x, y, W, H, R));
+  const double* s = S + static_cast<size_t>(p) * K;
+
+  double mu[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) mu[i] = RIDGE ? 0.0 : s[i] / Np;
+
+  // entry (i, j), i <= j, of the regularised system
+  auto A = [&](int i, int j) -> double {
+    if (!RIDGE) {
+      return s[NG + packed_index(i, j, NG)] / Np - mu[i] * mu[j] + (i == j ? eps : 0.0);
+    }
+    if (i == 0) return (j == 0) ? Np + eps : s[j - 1];
+    return s[NG + packed_index(i - 1, j - 1, NG)] + (i == j ? eps : 0.0);
+  };
+
+  double M[PD];
+  M[0] = 1.0 / A(0, 0);
+#pragma unroll
+  for (int kap = 1; kap < D; ++kap) {
+    double g[D];
+    double u[D];
+#pragma unroll
+    for (int i = 0; i < kap; ++i) g[i] = A(i, kap);
+#pragma unroll
+    for (int i = 0; i < kap; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < kap; ++j)
+        acc = fma(M[i <= j ? packed_index(i, j, D) : packed_index(j, i, D)], g[j], acc);
+      u[i] = acc;
+    }
+    double schur = A(kap, kap);
+#pragma unroll
+    for (int i = 0; i < kap; ++i) schur = fma(-g[i], u[i], schur);
+    const double inv = 1.0 / schur;
+#pragma unroll
+    for (int i = 0; i < kap; ++i) {
+      const double ui = u[i] * inv;
+#pragma unroll
+      for (int j = i; j < kap; ++j) M[packed_index(i, j, D)] = fma(ui, u[j], M[packed_index(i, j, D)]);
+      M[packed_index(i, kap, D)] = -ui;
+    }
+    M[packed_index(kap, kap, D)] = inv;
+  }
+  if (!RIDGE) {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) mu_out[static_cast<size_t>(p) * NG + i] = mu[i];
+  }
+#pragma unroll
+  for (int q = 0; q < PD; ++q) minv_out[static_cast<size_t>(p) * PD + q] = M[q];
+}
+
+// Same recursion over a batch of dense SPD matrices (upper triangle read).
+template <int D>
+__global__ __launch_bounds__(64) void spd_inverse_kernel(const double* __restrict__ a,
+                                                         double* __restrict__ out, int count) {
+  constexpr int PD = D * (D + 1) / 2;
+  const int b = static_cast<int>(blockIdx.x) * 64 + threadIdx.x;
+  if (b >= count) return;
+  const double* A = a + static_cast<size_t>(b) * D * D;
+  double M[PD];
+  M[0] = 1.0 / A[0];
+#pragma unroll
+  for (int kap = 1; kap < D; ++kap) {
+    double g[D];
+    double u[D];
+#pragma unroll
+    for (int i = 0; i < kap; ++i) g[i] = A[i * D + kap];
+#pragma unroll
+    for (int i = 0; i < kap; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < kap; ++j)
+        acc = fma(M[i <= j ? packed_index(i, j, D) : packed_index(j, i, D)], g[j], acc);
+      u[i] = acc;
+    }
+    double schur = A[kap * D + kap];
+#pragma unroll
+    for (int i = 0; i < kap; ++i) schur = fma(-g[i], u[i], schur);
+    const double inv = 1.0 / schur;
+#pragma unroll
+    for (int i = 0; i < kap; ++i) {
+      const double ui = u[i] * inv;
+#pragma unroll
+      for (int j = i; j < kap; ++j) M[packed_index(i, j, D)] = fma(ui, u[j], M[packed_index(i, j, D)]);
+      M[packed_index(i, kap, D)] = -ui;
+    }
+    M[packed_index(kap, kap, D)] = inv;
+  }
+  double* O = out + static_cast<size_t>(b) * D * D;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      O[i * D + j] = M[i <= j ? packed_index(i, j, D) : packed_index(j, i, D)];
+}
+
+}  // namespace
+
+hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t,
+                             double* partial, double* shift, bool centre, hipStream_t s) {
+  const int P = H * W;
+  hipLaunchKernelGGL(guide_mean_partial_kernel, dim3(kMeanBlocks), dim3(256), 0, s, I, P, t,
+                     partial);
+  hipLaunchKernelGGL(guide_mean_final_kernel, dim3(1), dim3(64), 0, s, partial, kMeanBlocks,
+                     t.n, P, centre ? 1 : 0, shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
+                              const double* shift, float* g32, double* g64, hipStream_t s) {
+  const int P = H * W;
+  const size_t total = static_cast<size_t>(P) * (t.n + 1);
+  const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+  hipLaunchKernelGGL(guide_synth_kernel, dim3(blocks), dim3(256), 0, s, I, P, t, shift, g32,
+                     g64);
+  return hipGetLastError();
+}
+
+template <int R>
+static hipError_t moments_r(const double* g64, int n, int H, int W, double* S, hipStream_t s) {
+  const int K = n + n * (n + 1) / 2;
+  StripGrid g = strip_grid(H, W, R, (K + 255) / 256, 2048);
+  dim3 grid(static_cast<unsigned>(g.strips * g.bands), static_cast<unsigned>((K + 255) / 256));
+  const int threads = K >= 256 ? 256 : ((K + 63) / 64) * 64;
+  hipLaunchKernelGGL(moments_kernel<R>, grid, dim3(threads), 0, s, g64, n, K, H, W, g.band_h,
+                     g.strips, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const double* g64, int n, int H, int W, int R, double* S,
+                          hipStream_t s) {
+  switch (R) {
+#define HGF_MOMENTS_CASE(r) \
+  case r:                   \
+    return moments_r<r>(g64, n, H, W, S, s);
+    HGF_MOMENTS_CASE(1)
+    HGF_MOMENTS_CASE(2)
+    HGF_MOMENTS_CASE(4)
+    HGF_MOMENTS_CASE(7)
+    HGF_MOMENTS_CASE(9)
+#undef HGF_MOMENTS_CASE
+    default:
+      return hipErrorNotSupported;
+  }
+}
+
+template <int D, int RIDGE>
+static hipError_t invert_d(const double* S, int H, int W, int R, double eps, double* mu,
+                           double* minv, hipStream_t s) {
+  const int P = H * W;
+  hipLaunchKernelGGL((invert_kernel<D, RIDGE>), dim3((P + 63) / 64), dim3(64), 0, s, S, H, W, R,
+                     eps, mu, minv);
+  return hipGetLastError();
+}
+
+hipError_t launch_invert(const double* S, int n, int H, int W, int R, double eps, int reg,
+                         double* mu, double* minv, hipStream_t s) {
+  if (reg == 0) {
+    switch (n) {
+#define HGF_INV_COV(d) \
+  case d:              \
+    return invert_d<d, 0>(S, H, W, R, eps, mu, minv, s);
+      HGF_INV_COV(1)
+      HGF_INV_COV(2)
+      HGF_INV_COV(3)
+      HGF_INV_COV(4)
+      HGF_INV_COV(5)
+      HGF_INV_COV(6)
+      HGF_INV_COV(7)
+      HGF_INV_COV(8)
+      HGF_INV_COV(9)
+      HGF_INV_COV(19)
+#undef HGF_INV_COV
+      default:
+        return hipErrorNotSupported;
+    }
+  }
+  switch (n + 1) {
+#define HGF_INV_RIDGE(d) \
+  case d:                \
+    return invert_d<d, 1>(S, H, W, R, eps, mu, minv, s);
+    HGF_INV_RIDGE(2)
+    HGF_INV_RIDGE(3)
+    HGF_INV_RIDGE(4)
+    HGF_INV_RIDGE(5)
+    HGF_INV_RIDGE(6)
+    HGF_INV_RIDGE(7)
+    HGF_INV_RIDGE(8)
+    HGF_INV_RIDGE(9)
+    HGF_INV_RIDGE(10)
+    HGF_INV_RIDGE(20)
+#undef HGF_INV_RIDGE
+    default:
+      return hipErrorNotSupported;
+  }
+}
+
+hipError_t launch_spd_inverse(const double* a, double* minv, int D, int count, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>((count + 63) / 64);
+  switch (D) {
+#define HGF_SPD(d)                                                                        \
+  case d:                                                                                 \
+    hipLaunchKernelGGL(spd_inverse_kernel<d>, dim3(blocks), dim3(64), 0, s, a, minv, count); \
+    return hipGetLastError();
+    HGF_SPD(1)
+    HGF_SPD(2)
+    HGF_SPD(3)
+    HGF_SPD(4)
+    HGF_SPD(5)
+    HGF_SPD(6)
+    HGF_SPD(7)
+    HGF_SPD(8)
+    HGF_SPD(9)
+    HGF_SPD(10)
+    HGF_SPD(11)
+    HGF_SPD(12)
+    HGF_SPD(13)
+    HGF_SPD(14)
+    HGF_SPD(15)
+    HGF_SPD(16)
+    HGF_SPD(17)
+    HGF_SPD(18)
+    HGF_SPD(19)
+    HGF_SPD(20)
+#undef HGF_SPD
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace hgf

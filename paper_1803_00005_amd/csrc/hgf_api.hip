@@ -1,0 +1,613 @@
+// C ABI of the HGF library: argument validation, workspace planning and the
+// launch sequence of the hot path.  See include/hgf.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hgf.h"
+#include "hgf_launch.hpp"
+
+namespace hgf {
+hipError_t launch_coef_n1(const CoefLaunch&, hipStream_t);
+hipError_t launch_coef_n2(const CoefLaunch&, hipStream_t);
+hipError_t launch_coef_n3(const CoefLaunch&, hipStream_t);
+hipError_t launch_coef_n4(const CoefLaunch&, hipStream_t);
+hipError_t launch_coef_n5(const CoefLaunch&, hipStream_t);
+hipError_t launch_coef_n6(const CoefLaunch&, hipStream_t);
+hipError_t launch_coef_n7(const CoefLaunch&, hipStream_t);
+hipError_t launch_coef_n8(const CoefLaunch&, hipStream_t);
+hipError_t launch_coef_n9(const CoefLaunch&, hipStream_t);
+hipError_t launch_coef_n19(const CoefLaunch&, hipStream_t);
+
+hipError_t launch_coef(const CoefLaunch& a, hipStream_t s) {
+  switch (a.n) {
+    case 1: return launch_coef_n1(a, s);
+    case 2: return launch_coef_n2(a, s);
+    case 3: return launch_coef_n3(a, s);
+    case 4: return launch_coef_n4(a, s);
+    case 5: return launch_coef_n5(a, s);
+    case 6: return launch_coef_n6(a, s);
+    case 7: return launch_coef_n7(a, s);
+    case 8: return launch_coef_n8(a, s);
+    case 9: return launch_coef_n9(a, s);
+    case 19: return launch_coef_n19(a, s);
+    default: return hipErrorNotSupported;
+  }
+}
+
+bool radius_supported(int R) { return R == 1 || R == 2 || R == 4 || R == 7 || R == 9; }
+
+bool config_supported(int n, int R, int reg) {
+  (void)reg;
+  const bool n_ok = (n >= 1 && n <= 9) || n == 19;
+  return n_ok && radius_supported(R);
+}
+
+// Output columns per strip of the coefficient kernel (state columns minus the halo).
+static int coef_strip_width(int n) { return (n + 1 > 10) ? 38 : 64; }
+
+StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_blocks) {
+  StripGrid g;
+  const int sout = sin - 2 * R;
+  g.strips = (W + sout - 1) / sout;
+  g.chunks = chunks;
+  const int per_band = std::max(1, g.strips * chunks);
+  int bands = std::max(1, (target_blocks + per_band - 1) / per_band);
+  int band_h = (H + bands - 1) / bands;
+  band_h = std::min(64, std::max(4, band_h));
+  g.band_h = band_h;
+  g.bands = (H + band_h - 1) / band_h;
+  return g;
+}
+
+StripGrid strip_grid(int H, int W, int R, int chunks, int target_blocks) {
+  return strip_grid_w(H, W, R, kStrip, chunks, target_blocks);
+}
+
+}  // namespace hgf
+
+using namespace hgf;
+
+// ----------------------------------------------------------------------------
+// errors
+// ----------------------------------------------------------------------------
+namespace {
+
+thread_local std::string g_last_error;
+
+hgf_status fail(hgf_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+hgf_status device_fail(hipError_t e, const char* where) {
+  if (e == hipErrorNotSupported)
+    return fail(HGF_E_UNSUPPORTED, std::string(where) + ": configuration not compiled in");
+  return fail(HGF_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HGF_TRY(expr, where)                       \
+  do {                                             \
+    hipError_t e_ = (expr);                        \
+    if (e_ != hipSuccess) return device_fail(e_, where); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int64_t binom(int a, int b) {
+  int64_t r = 1;
+  for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+  return r;
+}
+
+int num_channels_impl(int m, int d, int basis) {
+  if (m < 1 || m > 3 || d < 1 || d > 16) return -1;
+  if (basis == HGF_BASIS_POWER) return m * d;
+  if (basis == HGF_BASIS_MONOMIAL) return static_cast<int>(binom(m + d, d) - 1);
+  return -1;
+}
+
+// Exponents of the guidance channels (same order as the oracle and the header).
+bool build_table(int m, int d, int basis, MonoTable* t) {
+  std::memset(t, 0, sizeof(*t));
+  const int n = num_channels_impl(m, d, basis);
+  if (n < 1 || n > kMaxN) return false;
+  t->n = n;
+  t->m = m;
+  int k = 0;
+  if (basis == HGF_BASIS_POWER) {
+    for (int i = 0; i < m; ++i)
+      for (int j = 1; j <= d; ++j) t->e[k++][i] = static_cast<int8_t>(j);
+    return true;
+  }
+  for (int deg = 1; deg <= d; ++deg) {
+    // non-decreasing index sequences of length deg over m channels, lexicographic
+    std::vector<int> idx(deg, 0);
+    while (true) {
+      for (int c : idx) t->e[k][c] += 1;
+      ++k;
+      int pos = deg - 1;
+      while (pos >= 0 && idx[pos] == m - 1) --pos;
+      if (pos < 0) break;
+      const int v = idx[pos] + 1;
+      for (int q = pos; q < deg; ++q) idx[q] = v;
+    }
+  }
+  return k == n;
+}
+
+struct Plan {
+  int n = 0, D = 0, PD = 0, K = 0, P = 0, H = 0, W = 0, R = 0, L = 0;
+  int chunks_total = 0, chunks_per_launch = 0;
+  size_t off_partial = 0, off_shift = 0, off_g64 = 0, off_g32 = 0, off_mu = 0, off_minv = 0;
+  size_t off_x = 0, off_keys = 0, total = 0;
+  size_t ws_chunk_bytes = 0;
+  MonoTable table{};
+};
+
+constexpr size_t kWsCapBytes = size_t(12) << 30;  // coefficient workspace per launch group
+
+hgf_status validate(const hgf_params* p, MonoTable* table) {
+  if (p == nullptr) return fail(HGF_E_INVALID, "params is NULL");
+  if (p->height < 1 || p->width < 1) return fail(HGF_E_INVALID, "height and width must be >= 1");
+  if (static_cast<int64_t>(p->height) * p->width > (int64_t(1) << 30))
+    return fail(HGF_E_INVALID, "image too large");
+  if (p->guide_channels < 1 || p->guide_channels > 3)
+    return fail(HGF_E_INVALID, "guide_channels must be 1, 2 or 3");
+  if (p->degree < 1) return fail(HGF_E_INVALID, "degree must be >= 1");
+  if (p->basis != HGF_BASIS_MONOMIAL && p->basis != HGF_BASIS_POWER)
+    return fail(HGF_E_INVALID, "unknown basis");
+  if (p->reg != HGF_REG_COVARIANCE && p->reg != HGF_REG_RIDGE)
+    return fail(HGF_E_INVALID, "unknown regularisation");
+  if (p->radius < 0) return fail(HGF_E_INVALID, "radius must be >= 0");
+  if (p->num_labels < 1) return fail(HGF_E_INVALID, "num_labels must be >= 1");
+  if (!(p->eps > 0.0) || !std::isfinite(p->eps))
+    return fail(HGF_E_INVALID, "eps must be finite and > 0 (Prop. 1 divides by it)");
+  if (p->cost_dtype != HGF_F32 && p->cost_dtype != HGF_BF16)
+    return fail(HGF_E_INVALID, "cost_dtype must be HGF_F32 or HGF_BF16");
+  if (p->cost_ld != 0 && p->cost_ld < p->num_labels)
+    return fail(HGF_E_INVALID, "cost_ld must be 0 or >= num_labels");
+  if (p->out_ld != 0 && p->out_ld < p->num_labels)
+    return fail(HGF_E_INVALID, "out_ld must be 0 or >= num_labels");
+  if (p->reserved != 0) return fail(HGF_E_INVALID, "reserved must be 0");
+  const int n = num_channels_impl(p->guide_channels, p->degree, p->basis);
+  if (n < 1) return fail(HGF_E_INVALID, "invalid guide_channels/degree/basis");
+  if (!config_supported(n, p->radius, p->reg))
+    return fail(HGF_E_UNSUPPORTED, "n=" + std::to_string(n) + " radius=" +
+                                       std::to_string(p->radius) + " not compiled in");
+  if (p->reg == HGF_REG_RIDGE && p->cost_dtype != HGF_F32)
+    return fail(HGF_E_UNSUPPORTED, "ridge form is compiled for float32 costs only");
+  if (!build_table(p->guide_channels, p->degree, p->basis, table))
+    return fail(HGF_E_UNSUPPORTED, "guidance table");
+  return HGF_OK;
+}
+
+Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
+  Plan pl;
+  pl.table = table;
+  pl.n = table.n;
+  pl.D = p->reg == HGF_REG_RIDGE ? pl.n + 1 : pl.n;
+  pl.PD = pl.D * (pl.D + 1) / 2;
+  pl.K = pl.n + pl.n * (pl.n + 1) / 2;
+  pl.H = p->height;
+  pl.W = p->width;
+  pl.P = pl.H * pl.W;
+  pl.R = p->radius;
+  pl.L = p->num_labels;
+  pl.chunks_total = chunks_total;
+  pl.ws_chunk_bytes = static_cast<size_t>(pl.P) * (pl.n + 1) * 64 * sizeof(float);
+  pl.chunks_per_launch =
+      static_cast<int>(std::max<size_t>(1, std::min<size_t>(chunks_total, kWsCapBytes / pl.ws_chunk_bytes)));
+  size_t off = 0;
+  pl.off_partial = off;
+  off = align_up(off + sizeof(double) * kMeanBlocks * kMaxD);
+  pl.off_shift = off;
+  off = align_up(off + sizeof(double) * kMaxD);
+  pl.off_g64 = off;
+  off = align_up(off + sizeof(double) * static_cast<size_t>(pl.P) * pl.n);
+  pl.off_g32 = off;
+  off = align_up(off + sizeof(float) * static_cast<size_t>(pl.P) * (pl.n + 1));
+  pl.off_mu = off;
+  off = align_up(off + sizeof(double) * static_cast<size_t>(pl.P) * pl.n);
+  pl.off_minv = off;
+  off = align_up(off + sizeof(double) * static_cast<size_t>(pl.P) * pl.PD);
+  pl.off_x = off;
+  const size_t s_bytes = sizeof(double) * static_cast<size_t>(pl.P) * pl.K;
+  const size_t ws_bytes = pl.ws_chunk_bytes * pl.chunks_per_launch;
+  off = align_up(off + std::max(s_bytes, ws_bytes));
+  pl.off_keys = off;
+  off = align_up(off + sizeof(unsigned long long) * static_cast<size_t>(pl.P));
+  pl.total = off;
+  return pl;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+// Guidance part: a1..a3 into the plan's buffers.
+hgf_status run_guide(const Plan& pl, int reg, double eps, const float* guide, void* ws,
+                     hipStream_t s) {
+  HGF_TRY(launch_guide_mean(guide, pl.H, pl.W, pl.table, at<double>(ws, pl.off_partial),
+                            at<double>(ws, pl.off_shift), reg == HGF_REG_COVARIANCE, s),
+          "guide_mean");
+  HGF_TRY(launch_guide_synth(guide, pl.H, pl.W, pl.table, at<double>(ws, pl.off_shift),
+                             at<float>(ws, pl.off_g32), at<double>(ws, pl.off_g64), s),
+          "guide_synth");
+  HGF_TRY(launch_moments(at<double>(ws, pl.off_g64), pl.n, pl.H, pl.W, pl.R,
+                         at<double>(ws, pl.off_x), s),
+          "moments");
+  HGF_TRY(launch_invert(at<double>(ws, pl.off_x), pl.n, pl.H, pl.W, pl.R, eps, reg,
+                        at<double>(ws, pl.off_mu), at<double>(ws, pl.off_minv), s),
+          "invert");
+  return HGF_OK;
+}
+
+// Per-label part (a4..a7) for labels [l0, l0 + count) of the call's volume.
+hgf_status run_labels(const Plan& pl, int reg, int bf16, const void* cost, int cost_ld,
+                      float* out, int out_ld, unsigned long long* keys, int label_base,
+                      int count, const float* g32, const double* mu, const double* minv,
+                      float* wsbuf, hipStream_t s) {
+  const size_t esz = bf16 ? 2 : 4;
+  for (int l0 = 0; l0 < count; l0 += pl.chunks_per_launch * 64) {
+    const int lc = std::min(count - l0, pl.chunks_per_launch * 64);
+    const int chunks = (lc + 63) / 64;
+    CoefLaunch ca;
+    ca.cost = static_cast<const char*>(cost) + esz * l0;
+    ca.cost_bf16 = bf16;
+    ca.cost_ld = cost_ld;
+    ca.g32 = g32;
+    ca.mu = mu;
+    ca.minv = minv;
+    ca.ws = wsbuf;
+    ca.n = pl.n;
+    ca.H = pl.H;
+    ca.W = pl.W;
+    ca.R = pl.R;
+    ca.reg = reg;
+    ca.label_count = lc;
+    ca.grid = strip_grid_w(pl.H, pl.W, pl.R, coef_strip_width(pl.n), chunks, 512);
+    HGF_TRY(launch_coef(ca, s), "coef");
+    OutLaunch oa;
+    oa.ws = wsbuf;
+    oa.g32 = g32;
+    oa.out = out != nullptr ? out + l0 : nullptr;
+    oa.out_ld = out_ld;
+    oa.keys = keys;
+    oa.label_base = label_base + l0;
+    oa.n = pl.n;
+    oa.H = pl.H;
+    oa.W = pl.W;
+    oa.R = pl.R;
+    oa.label_count = lc;
+    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, kStrip, chunks, 512);
+    HGF_TRY(launch_out(oa, s), "out");
+  }
+  return HGF_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// context and device memory
+// ----------------------------------------------------------------------------
+struct hgf_context {
+  int device = 0;
+  size_t budget = 0;
+  size_t allocated = 0;
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+};
+
+// A resident guide owns one plan-sized device buffer: the guidance statistics
+// (g32, mu, minv) stay there between calls; the plan's shared region holds the
+// moment sums while the guide is created and the coefficient workspace of
+// later hgf_guide_filter calls.
+struct hgf_guide {
+  hgf_context* ctx = nullptr;
+  hgf_params params{};
+  Plan plan;
+  void* base = nullptr;
+  size_t bytes = 0;
+};
+
+namespace {
+
+hgf_status ctx_alloc(hgf_context* ctx, size_t bytes, void** out) {
+  if (ctx->budget != 0 && ctx->allocated + bytes > ctx->budget)
+    return fail(HGF_E_NOMEM, "device memory budget exceeded");
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(HGF_E_DEVICE, "hipGetDevice");
+  if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+    return fail(HGF_E_DEVICE, "hipSetDevice");
+  void* p = nullptr;
+  const hipError_t e = hipMalloc(&p, bytes);
+  if (cur != ctx->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HGF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  ctx->allocated += bytes;
+  *out = p;
+  return HGF_OK;
+}
+
+void ctx_free(hgf_context* ctx, void* p, size_t bytes) {
+  if (p == nullptr) return;
+  (void)hipFree(p);
+  ctx->allocated -= std::min(ctx->allocated, bytes);
+}
+
+hgf_status ctx_scratch(hgf_context* ctx, size_t bytes, void** out) {
+  if (ctx->scratch_bytes >= bytes) {
+    *out = ctx->scratch;
+    return HGF_OK;
+  }
+  // the previous scratch may still be in use by queued work on some stream
+  (void)hipDeviceSynchronize();
+  ctx_free(ctx, ctx->scratch, ctx->scratch_bytes);
+  ctx->scratch = nullptr;
+  ctx->scratch_bytes = 0;
+  void* p = nullptr;
+  const hgf_status st = ctx_alloc(ctx, bytes, &p);
+  if (st != HGF_OK) return st;
+  ctx->scratch = p;
+  ctx->scratch_bytes = bytes;
+  *out = p;
+  return HGF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hgf_num_channels(int32_t m, int32_t d, int32_t basis) {
+  return num_channels_impl(m, d, basis);
+}
+
+int32_t hgf_is_supported(int32_t n, int32_t radius, int32_t reg) {
+  return config_supported(n, radius, reg) ? 1 : 0;
+}
+
+hgf_status hgf_create(int32_t device, size_t hbm_budget_bytes, hgf_context** out) {
+  if (out == nullptr) return fail(HGF_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  const hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) return fail(HGF_E_DEVICE, "no HIP device");
+  if (device < 0 || device >= count) return fail(HGF_E_INVALID, "device index out of range");
+  hgf_context* ctx = new (std::nothrow) hgf_context();
+  if (ctx == nullptr) return fail(HGF_E_NOMEM, "host allocation");
+  ctx->device = device;
+  ctx->budget = hbm_budget_bytes;
+  *out = ctx;
+  return HGF_OK;
+}
+
+void hgf_destroy(hgf_context* ctx) {
+  if (ctx == nullptr) return;
+  if (ctx->scratch != nullptr) {
+    (void)hipDeviceSynchronize();
+    ctx_free(ctx, ctx->scratch, ctx->scratch_bytes);
+  }
+  delete ctx;
+}
+
+hgf_status hgf_workspace_size(const hgf_params* params, size_t* bytes) {
+  if (bytes == nullptr) return fail(HGF_E_INVALID, "bytes is NULL");
+  MonoTable t;
+  const hgf_status st = validate(params, &t);
+  if (st != HGF_OK) return st;
+  const Plan pl = make_plan(params, t, (params->num_labels + 63) / 64);
+  *bytes = pl.total;
+  return HGF_OK;
+}
+
+hgf_status hgf_filter(hgf_context* ctx, const hgf_params* params, const float* guide,
+                      const void* cost, float* out, int32_t* labels, void* workspace,
+                      size_t workspace_bytes, void* hip_stream) {
+  if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
+  MonoTable t;
+  hgf_status st = validate(params, &t);
+  if (st != HGF_OK) return st;
+  if (guide == nullptr || cost == nullptr) return fail(HGF_E_INVALID, "guide or cost is NULL");
+  if (out == nullptr && labels == nullptr)
+    return fail(HGF_E_INVALID, "out and labels are both NULL: nothing to compute");
+  const Plan pl = make_plan(params, t, (params->num_labels + 63) / 64);
+  void* ws = workspace;
+  if (ws == nullptr) {
+    st = ctx_scratch(ctx, pl.total, &ws);
+    if (st != HGF_OK) return st;
+  } else {
+    if (workspace_bytes < pl.total)
+      return fail(HGF_E_INVALID, "workspace smaller than hgf_workspace_size()");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0)
+      return fail(HGF_E_INVALID, "workspace must be 256-byte aligned");
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int cost_ld = params->cost_ld ? params->cost_ld : params->num_labels;
+  const int out_ld = params->out_ld ? params->out_ld : params->num_labels;
+  st = run_guide(pl, params->reg, params->eps, guide, ws, s);
+  if (st != HGF_OK) return st;
+  unsigned long long* keys = labels != nullptr ? at<unsigned long long>(ws, pl.off_keys) : nullptr;
+  if (keys != nullptr) HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
+  st = run_labels(pl, params->reg, params->cost_dtype == HGF_BF16, cost, cost_ld, out, out_ld,
+                  keys, 0, params->num_labels, at<float>(ws, pl.off_g32),
+                  at<double>(ws, pl.off_mu), at<double>(ws, pl.off_minv),
+                  at<float>(ws, pl.off_x), s);
+  if (st != HGF_OK) return st;
+  if (keys != nullptr)
+    HGF_TRY(launch_key_finalize(keys, pl.P, nullptr, labels, 0, s), "key_finalize");
+  return HGF_OK;
+}
+
+hgf_status hgf_guide_create(hgf_context* ctx, const hgf_params* params, const float* guide,
+                            void* hip_stream, hgf_guide** out) {
+  if (ctx == nullptr || out == nullptr) return fail(HGF_E_INVALID, "context or out is NULL");
+  *out = nullptr;
+  MonoTable t;
+  hgf_status st = validate(params, &t);
+  if (st != HGF_OK) return st;
+  if (guide == nullptr) return fail(HGF_E_INVALID, "guide is NULL");
+  hgf_guide* g = new (std::nothrow) hgf_guide();
+  if (g == nullptr) return fail(HGF_E_NOMEM, "host allocation");
+  g->ctx = ctx;
+  g->params = *params;
+  // label chunks processed per hgf_guide_filter launch group: one chunk of 64
+  g->plan = make_plan(params, t, 1);
+  const Plan& pl = g->plan;
+  g->bytes = pl.total;
+  st = ctx_alloc(ctx, g->bytes, &g->base);
+  if (st != HGF_OK) {
+    delete g;
+    return st;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  st = run_guide(pl, params->reg, params->eps, guide, g->base, s);
+  if (st != HGF_OK) {
+    (void)hipStreamSynchronize(s);
+    ctx_free(ctx, g->base, g->bytes);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return HGF_OK;
+}
+
+hgf_status hgf_guide_filter(hgf_context* ctx, hgf_guide* g, const void* cost_chunk,
+                            int32_t label_begin, int32_t label_count, int32_t ld,
+                            float* out_chunk, float* best_cost, int32_t* labels,
+                            void* hip_stream) {
+  if (ctx == nullptr || g == nullptr) return fail(HGF_E_INVALID, "context or guide is NULL");
+  if (cost_chunk == nullptr) return fail(HGF_E_INVALID, "cost_chunk is NULL");
+  if (label_count < 1 || label_begin < 0 ||
+      static_cast<int64_t>(label_begin) + label_count > g->params.num_labels)
+    return fail(HGF_E_INVALID, "label range outside [0, num_labels)");
+  if (ld != 0 && ld < label_count) return fail(HGF_E_INVALID, "ld must be 0 or >= label_count");
+  if ((best_cost == nullptr) != (labels == nullptr))
+    return fail(HGF_E_INVALID, "best_cost and labels must both be given or both be NULL");
+  if (out_chunk == nullptr && labels == nullptr)
+    return fail(HGF_E_INVALID, "out_chunk and labels are both NULL: nothing to compute");
+  const Plan& pl = g->plan;
+  const int ldv = ld ? ld : label_count;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  void* base = g->base;
+  unsigned long long* keys = labels != nullptr ? at<unsigned long long>(base, pl.off_keys) : nullptr;
+  if (keys != nullptr) HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
+  hgf_status st = run_labels(pl, g->params.reg, g->params.cost_dtype == HGF_BF16, cost_chunk,
+                             ldv, out_chunk, ldv, keys, label_begin, label_count,
+                             at<float>(base, pl.off_g32), at<double>(base, pl.off_mu),
+                             at<double>(base, pl.off_minv), at<float>(base, pl.off_x), s);
+  if (st != HGF_OK) return st;
+  if (keys != nullptr)
+    HGF_TRY(launch_key_finalize(keys, pl.P, best_cost, labels, label_begin > 0 ? 1 : 0, s),
+            "key_finalize");
+  return HGF_OK;
+}
+
+size_t hgf_guide_bytes(const hgf_guide* g) { return g != nullptr ? g->bytes : 0; }
+
+void hgf_guide_destroy(hgf_guide* g) {
+  if (g == nullptr) return;
+  (void)hipDeviceSynchronize();
+  ctx_free(g->ctx, g->base, g->bytes);
+  delete g;
+}
+
+hgf_status hgf_guide_export(const hgf_guide* g, double* mu, double* minv, double* shift,
+                            void* hip_stream) {
+  if (g == nullptr) return fail(HGF_E_INVALID, "guide is NULL");
+  const Plan& pl = g->plan;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (mu != nullptr)
+    HGF_TRY(hipMemcpyAsync(mu, at<char>(g->base, pl.off_mu),
+                           sizeof(double) * static_cast<size_t>(pl.P) * pl.n,
+                           hipMemcpyDeviceToDevice, s),
+            "export mu");
+  if (minv != nullptr)
+    HGF_TRY(hipMemcpyAsync(minv, at<char>(g->base, pl.off_minv),
+                           sizeof(double) * static_cast<size_t>(pl.P) * pl.PD,
+                           hipMemcpyDeviceToDevice, s),
+            "export minv");
+  if (shift != nullptr)
+    HGF_TRY(hipMemcpyAsync(shift, at<char>(g->base, pl.off_shift), sizeof(double) * pl.n,
+                           hipMemcpyDeviceToDevice, s),
+            "export shift");
+  return HGF_OK;
+}
+
+hgf_status hgf_filter_batch(hgf_context* ctx, int32_t count, const hgf_params* params,
+                            const float* const* guides, const void* const* costs,
+                            float* const* outs, int32_t* const* labels, void* hip_stream) {
+  if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
+  if (count < 0) return fail(HGF_E_INVALID, "count < 0");
+  if (count == 0) return HGF_OK;
+  if (params == nullptr || guides == nullptr || costs == nullptr)
+    return fail(HGF_E_INVALID, "params, guides or costs is NULL");
+  for (int i = 0; i < count; ++i) {
+    const hgf_status st = hgf_filter(ctx, &params[i], guides[i], costs[i],
+                                     outs != nullptr ? outs[i] : nullptr,
+                                     labels != nullptr ? labels[i] : nullptr, nullptr, 0,
+                                     hip_stream);
+    if (st != HGF_OK) return st;
+  }
+  return HGF_OK;
+}
+
+hgf_status hgf_box_sum(const float* in, float* out, int32_t channels, int32_t height,
+                       int32_t width, int32_t radius, void* hip_stream) {
+  if (in == nullptr || out == nullptr) return fail(HGF_E_INVALID, "in or out is NULL");
+  if (channels < 1 || height < 1 || width < 1 || radius < 0)
+    return fail(HGF_E_INVALID, "channels, height, width must be >= 1 and radius >= 0");
+  if (in == out) return fail(HGF_E_INVALID, "in and out must not overlap");
+  // the vertical pass needs a temporary image stack (the horizontal pass reads it)
+  const size_t bytes = sizeof(float) * static_cast<size_t>(channels) * height * width;
+  void* tmp = nullptr;
+  if (hipMalloc(&tmp, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HGF_E_NOMEM, "hipMalloc for the box-sum temporary");
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const hipError_t e = launch_box_sum(in, out, channels, height, width, radius,
+                                      static_cast<float*>(tmp), s);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return device_fail(e, "box_sum");
+  return HGF_OK;
+}
+
+hgf_status hgf_spd_inverse(const double* a, double* minv, int32_t dim, int32_t count,
+                           void* hip_stream) {
+  if (a == nullptr || minv == nullptr) return fail(HGF_E_INVALID, "a or minv is NULL");
+  if (dim < 1 || dim > kMaxD) return fail(HGF_E_INVALID, "dim must be in [1, 20]");
+  if (count < 0) return fail(HGF_E_INVALID, "count < 0");
+  if (count == 0) return HGF_OK;
+  HGF_TRY(launch_spd_inverse(a, minv, dim, count, static_cast<hipStream_t>(hip_stream)),
+          "spd_inverse");
+  return HGF_OK;
+}
+
+const char* hgf_status_string(hgf_status status) {
+  switch (status) {
+    case HGF_OK: return "HGF_OK";
+    case HGF_E_INVALID: return "HGF_E_INVALID";
+    case HGF_E_NOMEM: return "HGF_E_NOMEM";
+    case HGF_E_DEVICE: return "HGF_E_DEVICE";
+    case HGF_E_UNSUPPORTED: return "HGF_E_UNSUPPORTED";
+    case HGF_E_BUSY: return "HGF_E_BUSY";
+  }
+  return "unknown hgf_status";
+}
+
+const char* hgf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Device-side helpers shared by the HGF kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hgf {
+
+// Largest guidance channel count n the kernels are built for, and the largest
+// per-pixel system (ridge form adds the constant channel: D = n + 1).
+constexpr int kMaxN = 19;
+constexpr int kMaxD = 20;
+
+// State columns per strip in the strip kernels: one wavefront-width of columns.
+constexpr int kStrip = 64;
+
+// Read-only loads through the constant address space.  When the address is
+// wave-uniform the compiler emits scalar (SMEM) loads into SGPRs, so
+// per-pixel data shared by the 64 label lanes (the inverse M_p, the window
+// mean, the guidance value) costs no vector load and enters the VALU as a
+// scalar operand.
+template <typename T>
+__device__ __forceinline__ T ldu(const T* p, size_t i) {
+  typedef const __attribute__((address_space(4))) T* const_ptr;
+  return ((const_ptr)(p))[i];
+}
+
+// Exponent table of the polynomial guidance: channel k is
+// prod_c I_c^{e[k][c]} (Sec. 4.2).
+struct MonoTable {
+  int32_t n;
+  int32_t m;
+  int8_t e[kMaxD][4];
+};
+
+// Number of in-image pixels of the clipped (2R+1)^2 window centred at (x, y).
+__device__ __forceinline__ int window_count(int x, int y, int W, int H, int R) {
+  const int nx = min(x + R, W - 1) - max(x - R, 0) + 1;
+  const int ny = min(y + R, H - 1) - max(y - R, 0) + 1;
+  return nx * ny;
+}
+
+// Index of (i, j), i <= j, in the row-major packed upper triangle of a D x D matrix.
+__host__ __device__ constexpr int packed_index(int i, int j, int D) {
+  return i * D - (i * (i - 1)) / 2 + (j - i);
+}
+
+__device__ __forceinline__ float bf16_to_float(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ float load_cost(const T* p, size_t i);
+
+template <>
+__device__ __forceinline__ float load_cost<float>(const float* p, size_t i) {
+  return p[i];
+}
+
+template <>
+__device__ __forceinline__ float load_cost<uint16_t>(const uint16_t* p, size_t i) {
+  return bf16_to_float(p[i]);
+}
+
+// Order-preserving map of a float to uint32 (NaN canonicalised to +qNaN, which
+// sorts above +inf): a < b  <=>  ordered(a) < ordered(b).
+__device__ __forceinline__ uint32_t ordered_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if (f != f) u = 0x7fc00000u;
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float ordered_to_float(uint32_t u) {
+  const uint32_t b = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+  return __uint_as_float(b);
+}
+
+// (cost, label) key whose unsigned minimum is the lowest cost, lowest label on ties.
+__device__ __forceinline__ unsigned long long wta_key(float z, int label) {
+  return (static_cast<unsigned long long>(ordered_bits(z)) << 32) |
+         static_cast<unsigned long long>(static_cast<uint32_t>(label));
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long o = __shfl_xor(v, off, 64);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+}  // namespace hgf

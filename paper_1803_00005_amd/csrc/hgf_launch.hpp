@@ -1,0 +1,91 @@
+// Internal launch interface between the C ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hgf_device.hpp"
+
+namespace hgf {
+
+// Blocks of the deterministic two-stage reduction of the guidance means.
+constexpr int kMeanBlocks = 256;
+
+// Per-launch geometry of a strip kernel: strips of (64 - 2R) output columns,
+// bands of band_h output rows, label chunks of 64 lanes.
+struct StripGrid {
+  int strips;
+  int bands;
+  int band_h;
+  int chunks;
+};
+
+StripGrid strip_grid(int H, int W, int R, int chunks, int target_blocks);
+
+// Radii with compiled strip kernels.
+bool radius_supported(int R);
+// (n, R, reg) has compiled coefficient / output / inverse kernels.
+bool config_supported(int n, int R, int reg);
+
+// a1 + shift: guidance means (covariance form: each channel is shifted by its
+// image mean, an exact reformulation since the window covariance does not
+// see a constant offset; ridge form: no shift).
+hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t,
+                             double* partial, double* shift, bool centre,
+                             hipStream_t s);
+// a1: synthesized (shifted) guidance: float64 [P][n] and float32 [P][n+1] with
+// the constant channel G_0 = 1 first.
+hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
+                              const double* shift, float* g32, double* g64,
+                              hipStream_t s);
+// a2: window sums of G_i and G_i G_j (i <= j), float64 [P][K], K = n + n(n+1)/2.
+hipError_t launch_moments(const double* g64, int n, int H, int W, int R,
+                          double* S, hipStream_t s);
+// a3: per-pixel window mean mu [P][n] (covariance form) and the packed inverse
+// [P][D(D+1)/2] by the bordering recursion of Prop. 1, float64.
+hipError_t launch_invert(const double* S, int n, int H, int W, int R, double eps,
+                         int reg, double* mu, double* minv, hipStream_t s);
+
+struct CoefLaunch {
+  const void* cost;     // [H][W][cost_ld]
+  int cost_bf16;
+  int cost_ld;
+  const float* g32;     // [P][n+1], channel 0 = 1
+  const double* mu;     // [P][n]
+  const double* minv;   // [P][PD]
+  float* ws;            // [chunks][P][n+1][64]
+  int n, H, W, R, reg;
+  int label_count;      // labels in this launch (chunks = ceil(label_count / 64))
+  StripGrid grid;
+};
+// a4 + a5: per-label product box sums and coefficients a_l, b_l.
+hipError_t launch_coef(const CoefLaunch& a, hipStream_t s);
+
+struct OutLaunch {
+  const float* ws;      // [chunks][P][n+1][64]
+  const float* g32;     // [P][n+1], channel 0 = 1
+  float* out;           // [H][W][out_ld] or null
+  int out_ld;
+  unsigned long long* keys;  // [P] or null
+  int label_base;       // absolute label of lane 0 of chunk 0
+  int n, H, W, R;
+  int label_count;
+  StripGrid grid;
+};
+// a6 + a7: coefficient box filter, output and winner-takes-all keys.
+hipError_t launch_out(const OutLaunch& a, hipStream_t s);
+
+// Fill `count` keys with ~0 (no hipMemsetAsync: safe under graph capture).
+hipError_t launch_key_fill(unsigned long long* keys, size_t count, hipStream_t s);
+// labels / best cost from keys; merge != 0 keeps the incoming (best, label)
+// unless the key is strictly better.
+hipError_t launch_key_finalize(const unsigned long long* keys, size_t count,
+                               float* best, int32_t* labels, int merge,
+                               hipStream_t s);
+
+hipError_t launch_box_sum(const float* in, float* out, int C, int H, int W, int R,
+                          float* tmp, hipStream_t s);
+hipError_t launch_spd_inverse(const double* a, double* minv, int D, int count,
+                              hipStream_t s);
+
+}  // namespace hgf
