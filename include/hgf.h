@@ -153,12 +153,14 @@ void hgf_guide_destroy(hgf_guide* guide);
 
 /* Copy a resident guide's per-pixel statistics out (for inspection):
  *   mu    device float64 [H][W][n]   window means of the (shifted) guidance
- *   minv  device float64 [H][W][D(D+1)/2] packed upper triangle of the
- *         per-pixel inverse, row by row (D = n covariance, n + 1 ridge)
+ *   minv  device [H][W][D(D+1)/2] packed upper triangle of the per-pixel
+ *         inverse, row by row: D = n and float32 in the covariance form
+ *         (computed in float64, stored rounded), D = n + 1 and float64 in
+ *         the ridge form
  *   shift device float64 [n] the constant subtracted from each guidance
  *         channel (0 in ridge mode)
  * Any pointer may be NULL. */
-hgf_status hgf_guide_export(const hgf_guide* guide, double* mu, double* minv,
+hgf_status hgf_guide_export(const hgf_guide* guide, double* mu, void* minv,
                             double* shift, void* hip_stream);
 
 /* Filter `count` images of uneven size and label count (the batched form):
@@ -183,6 +185,20 @@ hgf_status hgf_box_sum(const float* in, float* out, int32_t channels,
  * is read); minv: device [count][D][D] (full symmetric result). 1 <= D <= 20. */
 hgf_status hgf_spd_inverse(const double* a, double* minv, int32_t dim,
                            int32_t count, void* hip_stream);
+
+/* Per-stage timing with HIP events, for measurement (off by default).  While
+ * enabled, hgf_filter, hgf_guide_create and hgf_guide_filter record an event
+ * before and after every kernel launch on the call's stream.
+ * hgf_stage_times waits for the recorded events, writes for each stage id
+ * s < max_stages the summed milliseconds ms[s] and the launch count
+ * launches[s] (either may be NULL), and clears the record.  Stage ids:
+ *   0 guidance means        1 guidance synthesis    2 guidance moment sums
+ *   3 per-pixel inverse     4 coefficients (a4-a5)  5 output and WTA (a6-a7)
+ *   6 WTA key fill/finalise */
+#define HGF_NUM_STAGES 7
+hgf_status hgf_set_stage_timing(hgf_context* ctx, int32_t enable);
+hgf_status hgf_stage_times(hgf_context* ctx, double* ms, int32_t* launches,
+                           int32_t max_stages);
 
 const char* hgf_status_string(hgf_status status);
 const char* hgf_last_error(void);

@@ -23,6 +23,8 @@
 // vertical sums, which bounds float32 drift to band_h + 2R additions.
 #pragma once
 
+#include <type_traits>
+
 #include "hgf_launch.hpp"
 
 namespace hgf {
@@ -30,24 +32,34 @@ namespace hgf {
 template <int R, int CPW, int NG, int RIDGE, typename TIN, int SIN>
 __global__ __launch_bounds__(640) void coef_kernel(
     const TIN* __restrict__ cost, int cost_ld, const float* __restrict__ g32,
-    const double* __restrict__ mu, const double* __restrict__ minv, float* __restrict__ ws,
+    const double* __restrict__ mu, const void* __restrict__ minv_void, float* __restrict__ ws,
     int H, int W, int label_count, int band_h, int strips, int bands) {
   constexpr int SOUT = SIN - 2 * R;
   constexpr int NCH = NG + 1;
   constexpr int NW = (NCH + CPW - 1) / CPW;
   constexpr int D = RIDGE ? NG + 1 : NG;
   constexpr int PD = D * (D + 1) / 2;
+  using MT = typename std::conditional<RIDGE != 0, double, float>::type;
+  const MT* __restrict__ minv = static_cast<const MT*>(minv_void);
+  // scalar loads of M are issued in blocks of this many elements (SMEM returns
+  // out of order, so a block is waited for as a whole)
+  constexpr int MBLK = RIDGE ? 32 : 64;
   constexpr int OC_RAW = 12800 / (NCH * 64);
   constexpr int OC = OC_RAW < 1 ? 1 : (OC_RAW > SOUT ? SOUT : OC_RAW);
   __shared__ float lds[OC * NCH * 64];
 
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int bid = static_cast<int>(blockIdx.x);
-  const int strip = bid % strips;
-  bid /= strips;
-  const int band = bid % bands;
-  const int chunk = bid / bands;
+  // work item of this block; integer division runs on the vector ALU, so the
+  // results are moved back to scalar registers explicitly
+  // logical order: label chunk fastest, then strip, then band (one XCD gets a
+  // contiguous range, so both label chunks of a strip share the L2 copy of M)
+  int bid = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int chunks = __builtin_amdgcn_readfirstlane(static_cast<int>(gridDim.x) / (strips * bands));
+  const int chunk = __builtin_amdgcn_readfirstlane(bid % chunks);
+  bid = __builtin_amdgcn_readfirstlane(bid / chunks);
+  const int strip = __builtin_amdgcn_readfirstlane(bid % strips);
+  const int band = __builtin_amdgcn_readfirstlane(bid / strips);
   const int x_out0 = strip * SOUT;
   const int xs = x_out0 - R;
   const int y0 = band * band_h;
@@ -64,28 +76,45 @@ __global__ __launch_bounds__(640) void coef_kernel(
 #pragma unroll
     for (int c = 0; c < SIN; ++c) vs[k][c] = 0.f;
 
-  // Vertical update with row yy for all state columns.  Branch-free: columns
-  // outside the image read a clamped pixel with weight 0.  The strip origin is
-  // laundered so that the per-column offsets are recomputed for each row
-  // rather than hoisted out of the row loop (64 live offsets would spill).
+  // Vertical update with row yy for all state columns, in groups of kGrp
+  // columns whose loads are all issued before they are used.  Columns outside
+  // the image read a clamped pixel (costs) or padding (guidance) and get weight
+  // 0 by a wave-uniform select.  The strip origin is laundered so that the
+  // per-column offsets are recomputed for each row rather than hoisted out of
+  // the row loop (64 live offsets would spill).
+  const size_t Pp = P;
   auto acc_row = [&](int yy, bool add) {
-    int xsl = xs;
+    int xsl = __builtin_amdgcn_readfirstlane(xs);
     asm volatile("" : "+s"(xsl));
-    const size_t rowp = static_cast<size_t>(yy) * W;
+    xsl = __builtin_amdgcn_readfirstlane(xsl);
+    const TIN* __restrict__ crow = cost + static_cast<size_t>(yy) * W * cost_ld;
+    const float* __restrict__ grow = g32 + static_cast<size_t>(yy) * W + xsl;
 #pragma unroll
-    for (int c = 0; c < SIN; ++c) {
-      if ((c & 7) == 0) __builtin_amdgcn_sched_barrier(0);
-      const int xr = xsl + c;
-      const int xc = min(max(xr, 0), W - 1);
-      const size_t p = rowp + xc;
-      const float yv = load_cost<TIN>(cost, p * cost_ld + labc);
+    for (int c0 = 0; c0 < SIN; c0 += kGrp) {
+      constexpr int G0 = kGrp;
+      float yv[G0];
+#pragma unroll
+      for (int c = 0; c < G0; ++c) {
+        if (c0 + c < SIN) {
+          const int xc = min(max(xsl + c0 + c, 0), W - 1);
+          yv[c] = load_cost<TIN>(crow, static_cast<uint32_t>(xc) * static_cast<uint32_t>(cost_ld) + labc);
+        }
+      }
 #pragma unroll
       for (int k = 0; k < CPW; ++k) {
         const int ch = wv * CPW + k;
         const int chc = ch < NCH ? ch : NCH - 1;
-        float g = ldu(g32, p * NCH + chc);
-        g = (xr == xc && ch < NCH) ? (add ? g : -g) : 0.f;
-        vs[k][c] = fmaf(g, yv, vs[k][c]);
+        const float* __restrict__ gp = grow + static_cast<size_t>(chc) * Pp + c0;
+#pragma unroll
+        for (int c = 0; c < G0; ++c) {
+          if (c0 + c < SIN) {
+            const int xr = xsl + c0 + c;
+            const float g = ldu(gp, c);
+            const bool ok = xr >= 0 && xr < W && ch < NCH;
+            const float gw = ok ? (add ? g : -g) : 0.f;
+            vs[k][c0 + c] = fmaf(gw, yv[c], vs[k][c0 + c]);
+          }
+        }
       }
     }
   };
@@ -95,31 +124,43 @@ __global__ __launch_bounds__(640) void coef_kernel(
     float T[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) T[ch] = lds[(q * NCH + ch) * 64 + lane];
-    double av[NG];
-    double b;
-    const double* __restrict__ mp = minv + p * PD;
+    const MT* __restrict__ mp = minv + p * PD;
+    float* __restrict__ o = wsc + p * NCH * 64 + lane;
     if (!RIDGE) {
+      // c = (T - mu U) / N in float64, then the product a = M c in float32
       const double invN = 1.0 / static_cast<double>(window_count(x, y, W, H, R));
       const double U = static_cast<double>(T[0]);
-      double c[NG];
-#pragma unroll
-      for (int i = 0; i < NG; ++i)
-        c[i] = (static_cast<double>(T[i + 1]) - ldu(mu, p * NG + i) * U) * invN;
-#pragma unroll
-      for (int i = 0; i < NG; ++i) av[i] = 0.0;
+      float c[NG];
+      float av[NG];
 #pragma unroll
       for (int i = 0; i < NG; ++i) {
-        __builtin_amdgcn_sched_barrier(0);
+        c[i] = static_cast<float>((static_cast<double>(T[i + 1]) - ldu(mu, p * NG + i) * U) * invN);
+        av[i] = 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
 #pragma unroll
         for (int j = i; j < NG; ++j) {
-          const double m = ldu(mp, packed_index(i, j, D));
-          av[i] = fma(m, c[j], av[i]);
-          if (j != i) av[j] = fma(m, c[i], av[j]);
+          const int qq = packed_index(i, j, D);
+          if (qq % MBLK == 0) __builtin_amdgcn_sched_barrier(0);
+          const float m = static_cast<float>(ldu(mp, qq));
+          av[i] = fmaf(m, c[j], av[i]);
+          if (j != i) av[j] = fmaf(m, c[i], av[j]);
         }
       }
-      b = U * invN;
+      __builtin_amdgcn_sched_barrier(0);
+      // intercept b = U / N - a . mu in float64; mu is read again (not kept
+      // live across the product, whose M block needs the scalar registers)
+      int pl = __builtin_amdgcn_readfirstlane(static_cast<int>(p));
+      asm volatile("" : "+s"(pl));
+      pl = __builtin_amdgcn_readfirstlane(pl);
+      double b = U * invN;
 #pragma unroll
-      for (int i = 0; i < NG; ++i) b = fma(-av[i], ldu(mu, p * NG + i), b);
+      for (int i = 0; i < NG; ++i)
+        b = fma(-static_cast<double>(av[i]), ldu(mu, static_cast<size_t>(pl) * NG + i), b);
+      o[0] = static_cast<float>(b);
+#pragma unroll
+      for (int i = 0; i < NG; ++i) o[(i + 1) * 64] = av[i];
     } else {
       double v[D];
       double w[D];
@@ -130,30 +171,39 @@ __global__ __launch_bounds__(640) void coef_kernel(
       }
 #pragma unroll
       for (int i = 0; i < D; ++i) {
-        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = i; j < D; ++j) {
-          const double m = ldu(mp, packed_index(i, j, D));
+          const int qq = packed_index(i, j, D);
+          if (qq % MBLK == 0) __builtin_amdgcn_sched_barrier(0);
+          const double m = static_cast<double>(ldu(mp, qq));
           w[i] = fma(m, v[j], w[i]);
           if (j != i) w[j] = fma(m, v[i], w[j]);
         }
       }
-      b = w[0];
 #pragma unroll
-      for (int i = 0; i < NG; ++i) av[i] = w[i + 1];
+      for (int i = 0; i < D; ++i) o[i * 64] = static_cast<float>(w[i]);
     }
-    float* __restrict__ o = wsc + p * NCH * 64 + lane;
-    o[0] = static_cast<float>(b);
-#pragma unroll
-    for (int i = 0; i < NG; ++i) o[(i + 1) * 64] = static_cast<float>(av[i]);
+  };
+
+  // Warm the L2 with the inverses of this row's output pixels (one vector
+  // load touching each of their cache lines), so the scalar loads of the
+  // product later hit L2 instead of HBM.
+  auto prefetch_minv = [&](int y) -> float {
+    constexpr int LINE_ELEMS = 128 / sizeof(MT);
+    const size_t first = (static_cast<size_t>(y) * W + x_out0) * PD;
+    const size_t total = static_cast<size_t>(min(SOUT, W - x_out0)) * PD;
+    const size_t e = static_cast<size_t>(lane + 64 * wv) * LINE_ELEMS;
+    return e < total ? static_cast<float>(minv[first + e]) : 0.f;
   };
 
   for (int yy = max(0, y0 - R); yy <= min(H - 1, y0 + R); ++yy) acc_row(yy, true);
   for (int y = y0; y < y1; ++y) {
+    const float pf = prefetch_minv(y);
     if (y > y0) {
       if (y + R < H) acc_row(y + R, true);
       if (y - R - 1 >= 0) acc_row(y - R - 1, false);
     }
+    asm volatile("" ::"v"(pf));
     double hs[CPW];
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
@@ -161,44 +211,50 @@ __global__ __launch_bounds__(640) void coef_kernel(
 #pragma unroll
       for (int c = 0; c <= 2 * R; ++c) hs[k] += static_cast<double>(vs[k][c]);
     }
+    // Output columns in LDS-sized chunks: the unrolled part touches only the
+    // register state (horizontal sums -> LDS); the solve runs after it as an
+    // ordinary loop, so the state array stays in registers.
+    constexpr int NCB = (SOUT + OC - 1) / OC;
 #pragma unroll
-    for (int j = 0; j < SOUT; ++j) {
-      if (j > 0) {
+    for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
-        for (int k = 0; k < CPW; ++k)
-          hs[k] += static_cast<double>(vs[k][j + 2 * R]) - static_cast<double>(vs[k][j - 1]);
-      }
-      const int jj = j % OC;
+      for (int jj = 0; jj < OC; ++jj) {
+        const int j = cb * OC + jj;
+        if (j < SOUT) {
+          if (j > 0) {
 #pragma unroll
-      for (int k = 0; k < CPW; ++k) {
-        const int ch = wv * CPW + k;
-        if (ch < NCH) lds[(jj * NCH + ch) * 64 + lane] = static_cast<float>(hs[k]);
-      }
-      if (jj == OC - 1 || j == SOUT - 1) {
-        __syncthreads();
-        const int j0 = j - jj;
-        for (int q = wv; q <= jj; q += NW) {
-          const int x = x_out0 + j0 + q;
-          if (x < W) solve_store(x, y, q);
+            for (int k = 0; k < CPW; ++k) {
+              // fresh conversions each step: keeping the converted values alive
+              // for 2R+1 steps would double the register footprint of the strip
+              float a = vs[k][j + 2 * R], b = vs[k][j - 1];
+              asm volatile("" : "+v"(a), "+v"(b));
+              hs[k] += static_cast<double>(a) - static_cast<double>(b);
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < CPW; ++k) {
+            const int ch = wv * CPW + k;
+            if (ch < NCH) lds[(jj * NCH + ch) * 64 + lane] = static_cast<float>(hs[k]);
+          }
         }
-        __syncthreads();
       }
+      __syncthreads();
+      const int cnt = min(OC, SOUT - cb * OC);
+      for (int q = wv; q < cnt; q += NW) {
+        const int x = x_out0 + cb * OC + q;
+        if (x < W) solve_store(x, y, q);
+      }
+      __syncthreads();
     }
   }
 }
-
-// Strip width (state columns) of the coefficient kernel.  Up to n = 9 one
-// channel per wave and 64 columns; above, two channels per wave and a
-// narrower strip so that ten waves fit the register file without spilling.
-template <int NG>
-constexpr int coef_strip() { return NG + 1 > 10 ? 38 : 64; }
 
 template <int R, int NG, int RIDGE, typename TIN>
 hipError_t coef_launch_t(const CoefLaunch& a, hipStream_t s) {
   constexpr int NCH = NG + 1;
   constexpr int CPW = NCH > 10 ? 2 : 1;
   constexpr int NW = (NCH + CPW - 1) / CPW;
-  constexpr int SIN = coef_strip<NG>();
+  constexpr int SIN = coef_strip_width(NG);
   const StripGrid& g = a.grid;
   const unsigned blocks = static_cast<unsigned>(g.strips * g.bands * g.chunks);
   hipLaunchKernelGGL((coef_kernel<R, CPW, NG, RIDGE, TIN, SIN>), dim3(blocks), dim3(NW * 64), 0, s,

@@ -5,6 +5,8 @@
 //   a3  per-pixel inverse of the regularised window system by the recursion
 //       of Prop. 1 (bordering form, branch-free: every Schur complement is
 //       at least the regulariser, so no pivot is ever needed).
+#include <type_traits>
+
 #include "hgf_launch.hpp"
 
 namespace hgf {
@@ -53,17 +55,26 @@ __global__ __launch_bounds__(256) void guide_mean_partial_kernel(
   }
 }
 
-__global__ void guide_mean_final_kernel(const double* __restrict__ partial, int nblocks, int n,
-                                        int P, int centre, double* __restrict__ shift) {
-  const int k = threadIdx.x;
-  if (k >= n) return;
-  double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[b * kMaxD + k];
-  shift[k] = centre ? s / static_cast<double>(P) : 0.0;
+__global__ __launch_bounds__(256) void guide_mean_final_kernel(
+    const double* __restrict__ partial, int nblocks, int n, int P, int centre,
+    double* __restrict__ shift) {
+  // one thread per partial block, fixed-order tree per channel (deterministic)
+  __shared__ double red[256];
+  for (int k = 0; k < n; ++k) {
+    red[threadIdx.x] = threadIdx.x < nblocks ? partial[threadIdx.x * kMaxD + k] : 0.0;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) shift[k] = centre ? red[0] / static_cast<double>(P) : 0.0;
+    __syncthreads();
+  }
 }
 
-// g32 holds n + 1 channels per pixel, channel 0 being the constant G_0 = 1, so
-// the per-label kernels index the multiplier of every box channel uniformly.
+// g32 holds n + 1 planar channels [n+1][P], channel 0 being the constant
+// G_0 = 1, so the per-label kernels index the multiplier of every box channel
+// uniformly and read 16 consecutive columns of one channel with one scalar load.
 __global__ __launch_bounds__(256) void guide_synth_kernel(
     const float* __restrict__ I, int P, MonoTable t, const double* __restrict__ shift,
     float* __restrict__ g32, double* __restrict__ g64) {
@@ -71,8 +82,8 @@ __global__ __launch_bounds__(256) void guide_synth_kernel(
   const size_t idx = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
   const size_t total = static_cast<size_t>(P) * n1;
   if (idx >= total) return;
-  const int p = static_cast<int>(idx / n1);
-  const int k = static_cast<int>(idx - static_cast<size_t>(p) * n1);
+  const int k = static_cast<int>(idx / P);
+  const int p = static_cast<int>(idx - static_cast<size_t>(k) * P);
   if (k == 0) {
     g32[idx] = 1.0f;
     return;
@@ -112,8 +123,9 @@ __global__ __launch_bounds__(256) void moments_kernel(
       cj = i + q;
     }
   }
-  const int strip = static_cast<int>(blockIdx.x) % strips;
-  const int band = static_cast<int>(blockIdx.x) / strips;
+  const int bid = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int strip = __builtin_amdgcn_readfirstlane(bid % strips);
+  const int band = __builtin_amdgcn_readfirstlane(bid / strips);
   const int x_out0 = strip * SOUT;
   const int xs = x_out0 - R;
   const int y0 = band * band_h;
@@ -128,22 +140,30 @@ __global__ __launch_bounds__(256) void moments_kernel(
   const int cjc = (kok && cj >= 0) ? cj : 0;
   const double jone = (kok && cj >= 0) ? 0.0 : 1.0;
 
-  // Branch-free vertical update: columns outside the image read a clamped
-  // pixel with weight 0; the strip origin is laundered so per-column offsets
-  // are not hoisted out of the row loop.
+  // Vertical update, kGrp columns of loads issued at a time; columns outside
+  // the image read a clamped pixel with weight 0.  The strip origin is
+  // laundered so per-column offsets are not hoisted out of the row loop.
   auto acc_row = [&](int yy, double sgn) {
-    int xsl = xs;
+    int xsl = __builtin_amdgcn_readfirstlane(xs);
     asm volatile("" : "+s"(xsl));
-    const size_t rowp = static_cast<size_t>(yy) * W;
+    xsl = __builtin_amdgcn_readfirstlane(xsl);
+    const double* __restrict__ row = g64 + static_cast<size_t>(yy) * W * n;
 #pragma unroll
-    for (int c = 0; c < kStrip; ++c) {
-      if ((c & 7) == 0) __builtin_amdgcn_sched_barrier(0);
-      const int xr = xsl + c;
-      const int xc = min(max(xr, 0), W - 1);
-      const size_t p = rowp + xc;
-      const double gi = g64[p * n + cic];
-      const double gj = fma(g64[p * n + cjc], 1.0 - jone, jone);
-      vs[c] = fma((xr == xc) ? sgn * gi : 0.0, gj, vs[c]);
+    for (int c0 = 0; c0 < kStrip; c0 += kGrp) {
+      double gi[kGrp], gj[kGrp];
+#pragma unroll
+      for (int c = 0; c < kGrp; ++c) {
+        const int xc = min(max(xsl + c0 + c, 0), W - 1);
+        const uint32_t o = static_cast<uint32_t>(xc) * static_cast<uint32_t>(n);
+        gi[c] = row[o + cic];
+        gj[c] = row[o + cjc];
+      }
+#pragma unroll
+      for (int c = 0; c < kGrp; ++c) {
+        const int xr = xsl + c0 + c;
+        const double w = (xr >= 0 && xr < W) ? sgn : 0.0;
+        vs[c0 + c] = fma(w * gi[c], fma(gj[c], 1.0 - jone, jone), vs[c0 + c]);
+      }
     }
   };
 
@@ -180,10 +200,15 @@ __global__ __launch_bounds__(256) void moments_kernel(
 // lambda -> eps (Sec. 5.1 applies the same inverse to Eq. 13).  Ridge form:
 // K -> raw window sums of [1, G][1, G]^T, lambda as given (Eq. 6).
 // ---------------------------------------------------------------------------
+// The inverse is computed in float64 and stored as float32 in the covariance
+// form (the per-label product M c is float32 there) and as float64 in the ridge
+// form, whose raw-sum systems are far worse conditioned.
 template <int D, int RIDGE>
 __global__ __launch_bounds__(64) void invert_kernel(
     const double* __restrict__ S, int H, int W, int R, double eps,
-    double* __restrict__ mu_out, double* __restrict__ minv_out) {
+    double* __restrict__ mu_out, void* __restrict__ minv_void) {
+  using MT = typename std::conditional<RIDGE != 0, double, float>::type;
+  MT* __restrict__ minv_out = static_cast<MT*>(minv_void);
   constexpr int NG = RIDGE ? D - 1 : D;             // guidance channels n
   constexpr int K = NG + NG * (NG + 1) / 2;
   constexpr int PD = D * (D + 1) / 2;
@@ -241,7 +266,7 @@ __global__ __launch_bounds__(64) void invert_kernel(
     for (int i = 0; i < NG; ++i) mu_out[static_cast<size_t>(p) * NG + i] = mu[i];
   }
 #pragma unroll
-  for (int q = 0; q < PD; ++q) minv_out[static_cast<size_t>(p) * PD + q] = M[q];
+  for (int q = 0; q < PD; ++q) minv_out[static_cast<size_t>(p) * PD + q] = static_cast<MT>(M[q]);
 }
 
 // Same recursion over a batch of dense SPD matrices (upper triangle read).
@@ -296,7 +321,7 @@ hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t,
   const int P = H * W;
   hipLaunchKernelGGL(guide_mean_partial_kernel, dim3(kMeanBlocks), dim3(256), 0, s, I, P, t,
                      partial);
-  hipLaunchKernelGGL(guide_mean_final_kernel, dim3(1), dim3(64), 0, s, partial, kMeanBlocks,
+  hipLaunchKernelGGL(guide_mean_final_kernel, dim3(1), dim3(256), 0, s, partial, kMeanBlocks,
                      t.n, P, centre ? 1 : 0, shift);
   return hipGetLastError();
 }
@@ -341,7 +366,7 @@ hipError_t launch_moments(const double* g64, int n, int H, int W, int R, double*
 
 template <int D, int RIDGE>
 static hipError_t invert_d(const double* S, int H, int W, int R, double eps, double* mu,
-                           double* minv, hipStream_t s) {
+                           void* minv, hipStream_t s) {
   const int P = H * W;
   hipLaunchKernelGGL((invert_kernel<D, RIDGE>), dim3((P + 63) / 64), dim3(64), 0, s, S, H, W, R,
                      eps, mu, minv);
@@ -349,7 +374,7 @@ static hipError_t invert_d(const double* S, int H, int W, int R, double eps, dou
 }
 
 hipError_t launch_invert(const double* S, int n, int H, int W, int R, double eps, int reg,
-                         double* mu, double* minv, hipStream_t s) {
+                         double* mu, void* minv, hipStream_t s) {
   if (reg == 0) {
     switch (n) {
 #define HGF_INV_COV(d) \

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -50,10 +51,20 @@ bool config_supported(int n, int R, int reg) {
   return n_ok && radius_supported(R);
 }
 
-// Output columns per strip of the coefficient kernel (state columns minus the halo).
-static int coef_strip_width(int n) { return (n + 1 > 10) ? 38 : 64; }
+// Tuning overrides for the strip decomposition (HGF_TARGET_BLOCKS,
+// HGF_MIN_BAND, HGF_MAX_BAND), read once; used by the measurement sweeps.
+static int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  if (v == nullptr || *v == 0) return dflt;
+  const int x = std::atoi(v);
+  return x > 0 ? x : dflt;
+}
 
 StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_blocks) {
+  static const int kTarget = env_int("HGF_TARGET_BLOCKS", 0);
+  static const int kMinBand = env_int("HGF_MIN_BAND", 4);
+  static const int kMaxBand = env_int("HGF_MAX_BAND", 64);
+  if (kTarget > 0) target_blocks = kTarget;
   StripGrid g;
   const int sout = sin - 2 * R;
   g.strips = (W + sout - 1) / sout;
@@ -61,7 +72,7 @@ StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_bloc
   const int per_band = std::max(1, g.strips * chunks);
   int bands = std::max(1, (target_blocks + per_band - 1) / per_band);
   int band_h = (H + bands - 1) / bands;
-  band_h = std::min(64, std::max(4, band_h));
+  band_h = std::min(kMaxBand, std::max(kMinBand, band_h));
   g.band_h = band_h;
   g.bands = (H + band_h - 1) / band_h;
   return g;
@@ -214,11 +225,11 @@ Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
   pl.off_g64 = off;
   off = align_up(off + sizeof(double) * static_cast<size_t>(pl.P) * pl.n);
   pl.off_g32 = off;
-  off = align_up(off + sizeof(float) * static_cast<size_t>(pl.P) * (pl.n + 1));
+  off = align_up(off + sizeof(float) * (static_cast<size_t>(pl.P) * (pl.n + 1) + 2 * kGPad));
   pl.off_mu = off;
   off = align_up(off + sizeof(double) * static_cast<size_t>(pl.P) * pl.n);
   pl.off_minv = off;
-  off = align_up(off + sizeof(double) * static_cast<size_t>(pl.P) * pl.PD);
+  off = align_up(off + static_cast<size_t>(minv_elem_bytes(p->reg)) * pl.P * pl.PD);
   pl.off_x = off;
   const size_t s_bytes = sizeof(double) * static_cast<size_t>(pl.P) * pl.K;
   const size_t ws_bytes = pl.ws_chunk_bytes * pl.chunks_per_launch;
@@ -234,28 +245,58 @@ T* at(void* base, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(base) + off);
 }
 
+}  // namespace
+
+struct hgf_context;
+namespace {
+struct StageTimer;
+}
+
+namespace {
+StageTimer* stage_timer_begin(hgf_context* ctx, int stage, hipStream_t s);
+void stage_timer_end(StageTimer* t);
+
+// RAII wrapper used by the launch sequences below
+struct Stage {
+  StageTimer* t;
+  Stage(hgf_context* ctx, int stage, hipStream_t s) : t(stage_timer_begin(ctx, stage, s)) {}
+  ~Stage() { stage_timer_end(t); }
+};
+
 // Guidance part: a1..a3 into the plan's buffers.
-hgf_status run_guide(const Plan& pl, int reg, double eps, const float* guide, void* ws,
-                     hipStream_t s) {
+hgf_status run_guide(hgf_context* ctx, const Plan& pl, int reg, double eps, const float* guide,
+                     void* ws, hipStream_t s) {
+  {
+  Stage st0(ctx, 0, s);
   HGF_TRY(launch_guide_mean(guide, pl.H, pl.W, pl.table, at<double>(ws, pl.off_partial),
                             at<double>(ws, pl.off_shift), reg == HGF_REG_COVARIANCE, s),
           "guide_mean");
+  }
+  {
+  Stage st1(ctx, 1, s);
   HGF_TRY(launch_guide_synth(guide, pl.H, pl.W, pl.table, at<double>(ws, pl.off_shift),
-                             at<float>(ws, pl.off_g32), at<double>(ws, pl.off_g64), s),
+                             at<float>(ws, pl.off_g32) + kGPad, at<double>(ws, pl.off_g64), s),
           "guide_synth");
+  }
+  {
+  Stage st2(ctx, 2, s);
   HGF_TRY(launch_moments(at<double>(ws, pl.off_g64), pl.n, pl.H, pl.W, pl.R,
                          at<double>(ws, pl.off_x), s),
           "moments");
+  }
+  {
+  Stage st3(ctx, 3, s);
   HGF_TRY(launch_invert(at<double>(ws, pl.off_x), pl.n, pl.H, pl.W, pl.R, eps, reg,
-                        at<double>(ws, pl.off_mu), at<double>(ws, pl.off_minv), s),
+                        at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv), s),
           "invert");
+  }
   return HGF_OK;
 }
 
 // Per-label part (a4..a7) for labels [l0, l0 + count) of the call's volume.
-hgf_status run_labels(const Plan& pl, int reg, int bf16, const void* cost, int cost_ld,
+hgf_status run_labels(hgf_context* ctx, const Plan& pl, int reg, int bf16, const void* cost, int cost_ld,
                       float* out, int out_ld, unsigned long long* keys, int label_base,
-                      int count, const float* g32, const double* mu, const double* minv,
+                      int count, const float* g32, const double* mu, const void* minv,
                       float* wsbuf, hipStream_t s) {
   const size_t esz = bf16 ? 2 : 4;
   for (int l0 = 0; l0 < count; l0 += pl.chunks_per_launch * 64) {
@@ -276,7 +317,10 @@ hgf_status run_labels(const Plan& pl, int reg, int bf16, const void* cost, int c
     ca.reg = reg;
     ca.label_count = lc;
     ca.grid = strip_grid_w(pl.H, pl.W, pl.R, coef_strip_width(pl.n), chunks, 512);
-    HGF_TRY(launch_coef(ca, s), "coef");
+    {
+      Stage st(ctx, 4, s);
+      HGF_TRY(launch_coef(ca, s), "coef");
+    }
     OutLaunch oa;
     oa.ws = wsbuf;
     oa.g32 = g32;
@@ -289,8 +333,11 @@ hgf_status run_labels(const Plan& pl, int reg, int bf16, const void* cost, int c
     oa.W = pl.W;
     oa.R = pl.R;
     oa.label_count = lc;
-    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, kStrip, chunks, 512);
-    HGF_TRY(launch_out(oa, s), "out");
+    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, out_strip_width(pl.n + 1 > 10 ? 2 : 1), chunks, 512);
+    {
+      Stage st(ctx, 5, s);
+      HGF_TRY(launch_out(oa, s), "out");
+    }
   }
   return HGF_OK;
 }
@@ -306,6 +353,14 @@ struct hgf_context {
   size_t allocated = 0;
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
+  // stage timing (hgf_set_stage_timing)
+  bool timing = false;
+  struct Rec {
+    int stage;
+    hipEvent_t start, stop;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> spare;
 };
 
 // A resident guide owns one plan-sized device buffer: the guidance statistics
@@ -321,6 +376,48 @@ struct hgf_guide {
 };
 
 namespace {
+
+hipEvent_t take_event(hgf_context* ctx) {
+  if (!ctx->spare.empty()) {
+    hipEvent_t e = ctx->spare.back();
+    ctx->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records an event pair around one launch when the context's timing is on.
+struct StageTimer {
+  hgf_context* ctx;
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  StageTimer(hgf_context* c, int st, hipStream_t stream) : ctx(c), stage(st), s(stream) {
+    if (ctx != nullptr && ctx->timing) {
+      a = take_event(ctx);
+      if (a != nullptr && hipEventRecord(a, s) != hipSuccess) a = nullptr;
+    }
+  }
+  ~StageTimer() {
+    if (a == nullptr) return;
+    hipEvent_t b = take_event(ctx);
+    if (b == nullptr || hipEventRecord(b, s) != hipSuccess) {
+      ctx->spare.push_back(a);
+      if (b != nullptr) ctx->spare.push_back(b);
+      return;
+    }
+    ctx->recs.push_back({stage, a, b});
+  }
+};
+
+StageTimer* stage_timer_begin(hgf_context* ctx, int stage, hipStream_t s) {
+  if (ctx == nullptr || !ctx->timing) return nullptr;
+  return new (std::nothrow) StageTimer(ctx, stage, s);
+}
+
+void stage_timer_end(StageTimer* t) { delete t; }
 
 hgf_status ctx_alloc(hgf_context* ctx, size_t bytes, void** out) {
   if (ctx->budget != 0 && ctx->allocated + bytes > ctx->budget)
@@ -395,6 +492,12 @@ hgf_status hgf_create(int32_t device, size_t hbm_budget_bytes, hgf_context** out
 
 void hgf_destroy(hgf_context* ctx) {
   if (ctx == nullptr) return;
+  (void)hipDeviceSynchronize();
+  for (auto& r : ctx->recs) {
+    ctx->spare.push_back(r.start);
+    ctx->spare.push_back(r.stop);
+  }
+  for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
   if (ctx->scratch != nullptr) {
     (void)hipDeviceSynchronize();
     ctx_free(ctx, ctx->scratch, ctx->scratch_bytes);
@@ -436,17 +539,22 @@ hgf_status hgf_filter(hgf_context* ctx, const hgf_params* params, const float* g
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int cost_ld = params->cost_ld ? params->cost_ld : params->num_labels;
   const int out_ld = params->out_ld ? params->out_ld : params->num_labels;
-  st = run_guide(pl, params->reg, params->eps, guide, ws, s);
+  st = run_guide(ctx, pl, params->reg, params->eps, guide, ws, s);
   if (st != HGF_OK) return st;
   unsigned long long* keys = labels != nullptr ? at<unsigned long long>(ws, pl.off_keys) : nullptr;
-  if (keys != nullptr) HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
-  st = run_labels(pl, params->reg, params->cost_dtype == HGF_BF16, cost, cost_ld, out, out_ld,
-                  keys, 0, params->num_labels, at<float>(ws, pl.off_g32),
-                  at<double>(ws, pl.off_mu), at<double>(ws, pl.off_minv),
+  if (keys != nullptr) {
+    Stage sk(ctx, 6, s);
+    HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
+  }
+  st = run_labels(ctx, pl, params->reg, params->cost_dtype == HGF_BF16, cost, cost_ld, out, out_ld,
+                  keys, 0, params->num_labels, at<float>(ws, pl.off_g32) + kGPad,
+                  at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv),
                   at<float>(ws, pl.off_x), s);
   if (st != HGF_OK) return st;
-  if (keys != nullptr)
+  if (keys != nullptr) {
+    Stage sk(ctx, 6, s);
     HGF_TRY(launch_key_finalize(keys, pl.P, nullptr, labels, 0, s), "key_finalize");
+  }
   return HGF_OK;
 }
 
@@ -472,7 +580,7 @@ hgf_status hgf_guide_create(hgf_context* ctx, const hgf_params* params, const fl
     return st;
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  st = run_guide(pl, params->reg, params->eps, guide, g->base, s);
+  st = run_guide(ctx, pl, params->reg, params->eps, guide, g->base, s);
   if (st != HGF_OK) {
     (void)hipStreamSynchronize(s);
     ctx_free(ctx, g->base, g->bytes);
@@ -502,15 +610,20 @@ hgf_status hgf_guide_filter(hgf_context* ctx, hgf_guide* g, const void* cost_chu
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   void* base = g->base;
   unsigned long long* keys = labels != nullptr ? at<unsigned long long>(base, pl.off_keys) : nullptr;
-  if (keys != nullptr) HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
-  hgf_status st = run_labels(pl, g->params.reg, g->params.cost_dtype == HGF_BF16, cost_chunk,
+  if (keys != nullptr) {
+    Stage sk(ctx, 6, s);
+    HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
+  }
+  hgf_status st = run_labels(ctx, pl, g->params.reg, g->params.cost_dtype == HGF_BF16, cost_chunk,
                              ldv, out_chunk, ldv, keys, label_begin, label_count,
-                             at<float>(base, pl.off_g32), at<double>(base, pl.off_mu),
-                             at<double>(base, pl.off_minv), at<float>(base, pl.off_x), s);
+                             at<float>(base, pl.off_g32) + kGPad, at<double>(base, pl.off_mu),
+                             at<char>(base, pl.off_minv), at<float>(base, pl.off_x), s);
   if (st != HGF_OK) return st;
-  if (keys != nullptr)
+  if (keys != nullptr) {
+    Stage sk(ctx, 6, s);
     HGF_TRY(launch_key_finalize(keys, pl.P, best_cost, labels, label_begin > 0 ? 1 : 0, s),
             "key_finalize");
+  }
   return HGF_OK;
 }
 
@@ -523,7 +636,7 @@ void hgf_guide_destroy(hgf_guide* g) {
   delete g;
 }
 
-hgf_status hgf_guide_export(const hgf_guide* g, double* mu, double* minv, double* shift,
+hgf_status hgf_guide_export(const hgf_guide* g, double* mu, void* minv, double* shift,
                             void* hip_stream) {
   if (g == nullptr) return fail(HGF_E_INVALID, "guide is NULL");
   const Plan& pl = g->plan;
@@ -535,7 +648,7 @@ hgf_status hgf_guide_export(const hgf_guide* g, double* mu, double* minv, double
             "export mu");
   if (minv != nullptr)
     HGF_TRY(hipMemcpyAsync(minv, at<char>(g->base, pl.off_minv),
-                           sizeof(double) * static_cast<size_t>(pl.P) * pl.PD,
+                           static_cast<size_t>(minv_elem_bytes(g->params.reg)) * pl.P * pl.PD,
                            hipMemcpyDeviceToDevice, s),
             "export minv");
   if (shift != nullptr)
@@ -594,6 +707,35 @@ hgf_status hgf_spd_inverse(const double* a, double* minv, int32_t dim, int32_t c
   HGF_TRY(launch_spd_inverse(a, minv, dim, count, static_cast<hipStream_t>(hip_stream)),
           "spd_inverse");
   return HGF_OK;
+}
+
+hgf_status hgf_set_stage_timing(hgf_context* ctx, int32_t enable) {
+  if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
+  ctx->timing = enable != 0;
+  return HGF_OK;
+}
+
+hgf_status hgf_stage_times(hgf_context* ctx, double* ms, int32_t* launches, int32_t max_stages) {
+  if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
+  if (max_stages < 0) return fail(HGF_E_INVALID, "max_stages < 0");
+  for (int i = 0; i < max_stages; ++i) {
+    if (ms != nullptr) ms[i] = 0.0;
+    if (launches != nullptr) launches[i] = 0;
+  }
+  hgf_status st = HGF_OK;
+  for (auto& r : ctx->recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess)
+      st = fail(HGF_E_DEVICE, "stage event timing");
+    if (r.stage < max_stages) {
+      if (ms != nullptr) ms[r.stage] += t;
+      if (launches != nullptr) launches[r.stage] += 1;
+    }
+    ctx->spare.push_back(r.start);
+    ctx->spare.push_back(r.stop);
+  }
+  ctx->recs.clear();
+  return st;
 }
 
 const char* hgf_status_string(hgf_status status) {

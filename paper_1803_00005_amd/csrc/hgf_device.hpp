@@ -14,6 +14,15 @@ constexpr int kMaxD = 20;
 // State columns per strip in the strip kernels: one wavefront-width of columns.
 constexpr int kStrip = 64;
 
+// Columns whose loads a strip kernel issues together before using them.
+constexpr int kGrp = 16;
+
+// Floats of padding before and after the planar float32 guidance [n+1][P]:
+// a strip reads 16 consecutive columns of a row with one scalar load, and the
+// columns of a group that fall outside the image (at most 31 on either side)
+// read padding or a neighbouring row; their weight is selected to 0.
+constexpr int kGPad = 64;
+
 // Read-only loads through the constant address space.  When the address is
 // wave-uniform the compiler emits scalar (SMEM) loads into SGPRs, so
 // per-pixel data shared by the 64 label lanes (the inverse M_p, the window

@@ -21,6 +21,14 @@ struct StripGrid {
 };
 
 StripGrid strip_grid(int H, int W, int R, int chunks, int target_blocks);
+StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_blocks);
+
+// State columns per strip of the coefficient kernel: up to n = 9 one channel
+// per wave and 64 columns; above, two channels per wave and a narrower strip
+// so that ten waves fit the register file.
+constexpr int coef_strip_width(int n) { return n + 1 > 10 ? 38 : 64; }
+// State columns per strip of the output kernel for 1 or 2 channels per wave.
+constexpr int out_strip_width(int cpw) { return cpw > 1 ? 32 : 64; }
 
 // Radii with compiled strip kernels.
 bool radius_supported(int R);
@@ -33,8 +41,9 @@ bool config_supported(int n, int R, int reg);
 hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t,
                              double* partial, double* shift, bool centre,
                              hipStream_t s);
-// a1: synthesized (shifted) guidance: float64 [P][n] and float32 [P][n+1] with
-// the constant channel G_0 = 1 first.
+// a1: synthesized (shifted) guidance: float64 [P][n] and planar float32
+// [n+1][P] with the constant channel G_0 = 1 first (g32 points at channel 0;
+// the allocation has kGPad floats before and after).
 hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
                               const double* shift, float* g32, double* g64,
                               hipStream_t s);
@@ -42,17 +51,32 @@ hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
 hipError_t launch_moments(const double* g64, int n, int H, int W, int R,
                           double* S, hipStream_t s);
 // a3: per-pixel window mean mu [P][n] (covariance form) and the packed inverse
-// [P][D(D+1)/2] by the bordering recursion of Prop. 1, float64.
+// [P][D(D+1)/2] by the bordering recursion of Prop. 1, computed in float64 and
+// stored as float32 (covariance form) or float64 (ridge form).
 hipError_t launch_invert(const double* S, int n, int H, int W, int R, double eps,
-                         int reg, double* mu, double* minv, hipStream_t s);
+                         int reg, double* mu, void* minv, hipStream_t s);
+
+// Bytes per stored inverse element.
+constexpr int minv_elem_bytes(int reg) { return reg == 0 ? 4 : 8; }
+
+// Logical block index of hardware block `bid` of `nb`: consecutive hardware
+// blocks are dispatched round-robin over the 8 XCDs, so this hands each XCD a
+// contiguous range of logical work items (neighbouring strips and label
+// chunks of one strip then share that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int full = nb & ~7;
+  if (bid >= full) return bid;
+  const int per = full >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
 
 struct CoefLaunch {
   const void* cost;     // [H][W][cost_ld]
   int cost_bf16;
   int cost_ld;
-  const float* g32;     // [P][n+1], channel 0 = 1
+  const float* g32;     // planar [n+1][P], channel 0 = 1, padded
   const double* mu;     // [P][n]
-  const double* minv;   // [P][PD]
+  const void* minv;     // [P][PD] float32 (covariance) or float64 (ridge)
   float* ws;            // [chunks][P][n+1][64]
   int n, H, W, R, reg;
   int label_count;      // labels in this launch (chunks = ceil(label_count / 64))
@@ -63,7 +87,7 @@ hipError_t launch_coef(const CoefLaunch& a, hipStream_t s);
 
 struct OutLaunch {
   const float* ws;      // [chunks][P][n+1][64]
-  const float* g32;     // [P][n+1], channel 0 = 1
+  const float* g32;     // planar [n+1][P], channel 0 = 1, padded
   float* out;           // [H][W][out_ld] or null
   int out_ld;
   unsigned long long* keys;  // [P] or null

@@ -20,12 +20,11 @@ namespace {
 
 constexpr int kOutMaxWaves = 10;
 
-template <int R, int CPW>
+template <int R, int CPW, int SIN>
 __global__ __launch_bounds__(640) void out_kernel(
     const float* __restrict__ ws, const float* __restrict__ g32, float* __restrict__ out,
     int out_ld, unsigned long long* __restrict__ keys, int label_base, int n, int H, int W,
     int label_count, int band_h, int strips, int bands) {
-  constexpr int SIN = kStrip;
   constexpr int SOUT = SIN - 2 * R;
   constexpr int OC = SOUT < 10 ? SOUT : 10;
   __shared__ double part[kOutMaxWaves * OC * 64];
@@ -34,11 +33,14 @@ __global__ __launch_bounds__(640) void out_kernel(
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int NW = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
-  int bid = static_cast<int>(blockIdx.x);
-  const int strip = bid % strips;
-  bid /= strips;
-  const int band = bid % bands;
-  const int chunk = bid / bands;
+  // work item of this block; integer division runs on the vector ALU, so the
+  // results are moved back to scalar registers explicitly
+  int bid = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int chunks = __builtin_amdgcn_readfirstlane(static_cast<int>(gridDim.x) / (strips * bands));
+  const int chunk = __builtin_amdgcn_readfirstlane(bid % chunks);
+  bid = __builtin_amdgcn_readfirstlane(bid / chunks);
+  const int strip = __builtin_amdgcn_readfirstlane(bid % strips);
+  const int band = __builtin_amdgcn_readfirstlane(bid / strips);
   const int x_out0 = strip * SOUT;
   const int xs = x_out0 - R;
   const int y0 = band * band_h;
@@ -54,23 +56,38 @@ __global__ __launch_bounds__(640) void out_kernel(
 #pragma unroll
     for (int c = 0; c < SIN; ++c) vs[k][c] = 0.f;
 
+  // Vertical update with row yy, kGrp columns of loads issued at a time;
+  // columns outside the image read a clamped pixel with weight 0.
   auto acc_row = [&](int yy, bool add) {
-    int xsl = xs;
+    int xsl = __builtin_amdgcn_readfirstlane(xs);
     asm volatile("" : "+s"(xsl));
-    const size_t rowp = static_cast<size_t>(yy) * W;
+    xsl = __builtin_amdgcn_readfirstlane(xsl);
+    // uniform row base + lane offset: loads use an SGPR base and one VGPR offset
+    const float* __restrict__ row = wsc + static_cast<size_t>(yy) * W * NCH * 64;
+    constexpr int GRP = CPW > 1 ? kGrp / 2 : kGrp;
 #pragma unroll
-    for (int c = 0; c < SIN; ++c) {
-      if ((c & 7) == 0) __builtin_amdgcn_sched_barrier(0);
-      const int xr = xsl + c;
-      const int xc = min(max(xr, 0), W - 1);
-      const size_t p = rowp + xc;
+    for (int c0 = 0; c0 < SIN; c0 += GRP) {
+      float v[CPW][GRP];
 #pragma unroll
-      for (int k = 0; k < CPW; ++k) {
-        const int ch = wv * CPW + k;
-        const int chc = ch < NCH ? ch : NCH - 1;
-        const float v = wsc[(p * NCH + chc) * 64 + lane];
-        const float w = (xr == xc && ch < NCH) ? (add ? 1.f : -1.f) : 0.f;
-        vs[k][c] = fmaf(w, v, vs[k][c]);
+      for (int c = 0; c < GRP; ++c) {
+        const int xc = min(max(xsl + c0 + c, 0), W - 1);
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+          const int ch = wv * CPW + k;
+          const int chc = ch < NCH ? ch : NCH - 1;
+          v[k][c] = row[(static_cast<uint32_t>(xc) * NCH + chc) * 64u + lane];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < GRP; ++c) {
+        const int xr = xsl + c0 + c;
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+          const int ch = wv * CPW + k;
+          const bool ok = xr >= 0 && xr < W && ch < NCH;
+          const float w = ok ? (add ? 1.f : -1.f) : 0.f;
+          vs[k][c0 + c] = fmaf(w, v[k][c], vs[k][c0 + c]);
+        }
       }
     }
   };
@@ -88,48 +105,57 @@ __global__ __launch_bounds__(640) void out_kernel(
 #pragma unroll
       for (int c = 0; c <= 2 * R; ++c) hs[k] += static_cast<double>(vs[k][c]);
     }
+    // Output columns in chunks of OC: the unrolled part touches only the
+    // register state; the reduction over waves runs after it as a plain loop.
+    constexpr int NCB = (SOUT + OC - 1) / OC;
+    const size_t prow = static_cast<size_t>(y) * W + x_out0;
 #pragma unroll
-    for (int j = 0; j < SOUT; ++j) {
-      if (j > 0) {
+    for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
-        for (int k = 0; k < CPW; ++k)
-          hs[k] += static_cast<double>(vs[k][j + 2 * R]) - static_cast<double>(vs[k][j - 1]);
-      }
-      const int jj = j % OC;
-      {
-        const int x = min(x_out0 + j, W - 1);
-        const size_t p = static_cast<size_t>(y) * W + x;
-        double pj = 0.0;
+      for (int jj = 0; jj < OC; ++jj) {
+        const int j = cb * OC + jj;
+        if (j < SOUT) {
+          if (j > 0) {
 #pragma unroll
-        for (int k = 0; k < CPW; ++k) {
-          const int ch = wv * CPW + k;
-          const int chc = ch < NCH ? ch : NCH - 1;
-          const double g = ch < NCH ? static_cast<double>(ldu(g32, p * NCH + chc)) : 0.0;
-          pj = fma(hs[k], g, pj);
-        }
-        part[(wv * OC + jj) * 64 + lane] = pj;
-      }
-      if (jj == OC - 1 || j == SOUT - 1) {
-        __syncthreads();
-        const int j0 = j - jj;
-        for (int q = wv; q <= jj; q += NW) {
-          const int x = x_out0 + j0 + q;
-          if (x < W) {
-            const size_t p = static_cast<size_t>(y) * W + x;
-            double z = 0.0;
-            for (int w = 0; w < NW; ++w) z += part[(w * OC + q) * 64 + lane];
-            z /= static_cast<double>(window_count(x, y, W, H, R));
-            const float zf = static_cast<float>(z);
-            if (out != nullptr && lab_ok) out[p * out_ld + lab] = zf;
-            if (keys != nullptr) {
-              unsigned long long key = lab_ok ? wta_key(zf, label_base + lab) : ~0ull;
-              key = wave_min_u64(key);
-              if (lane == 0) atomicMin(&keys[p], key);
+            for (int k = 0; k < CPW; ++k) {
+              // fresh conversions each step (see the coefficient kernel)
+              float a = vs[k][j + 2 * R], b = vs[k][j - 1];
+              asm volatile("" : "+v"(a), "+v"(b));
+              hs[k] += static_cast<double>(a) - static_cast<double>(b);
             }
           }
+          // guidance at output column x_out0 + j (planar, consecutive in j;
+          // columns past the image read padding and their partials are unused)
+          double pj = 0.0;
+#pragma unroll
+          for (int k = 0; k < CPW; ++k) {
+            const int ch = wv * CPW + k;
+            const int chc = ch < NCH ? ch : NCH - 1;
+            const float g = ldu(g32 + static_cast<size_t>(chc) * P + prow, j);
+            pj = fma(hs[k], ch < NCH ? static_cast<double>(g) : 0.0, pj);
+          }
+          part[(wv * OC + jj) * 64 + lane] = pj;
         }
-        __syncthreads();
       }
+      __syncthreads();
+      const int cnt = min(OC, SOUT - cb * OC);
+      for (int q = wv; q < cnt; q += NW) {
+        const int x = x_out0 + cb * OC + q;
+        if (x < W) {
+          const size_t p = static_cast<size_t>(y) * W + x;
+          double z = 0.0;
+          for (int w = 0; w < NW; ++w) z += part[(w * OC + q) * 64 + lane];
+          z /= static_cast<double>(window_count(x, y, W, H, R));
+          const float zf = static_cast<float>(z);
+          if (out != nullptr && lab_ok) out[p * out_ld + lab] = zf;
+          if (keys != nullptr) {
+            unsigned long long key = lab_ok ? wta_key(zf, label_base + lab) : ~0ull;
+            key = wave_min_u64(key);
+            if (lane == 0) atomicMin(&keys[p], key);
+          }
+        }
+      }
+      __syncthreads();
     }
   }
 }
@@ -194,11 +220,12 @@ __global__ __launch_bounds__(256) void box_horizontal_kernel(const float* __rest
 
 template <int R, int CPW>
 hipError_t out_launch_t(const OutLaunch& a, hipStream_t s) {
+  constexpr int SIN = out_strip_width(CPW);
   const int NCH = a.n + 1;
   const int NW = (NCH + CPW - 1) / CPW;
   const StripGrid& g = a.grid;
   const unsigned blocks = static_cast<unsigned>(g.strips * g.bands * g.chunks);
-  hipLaunchKernelGGL((out_kernel<R, CPW>), dim3(blocks), dim3(NW * 64), 0, s, a.ws, a.g32, a.out,
+  hipLaunchKernelGGL((out_kernel<R, CPW, SIN>), dim3(blocks), dim3(NW * 64), 0, s, a.ws, a.g32, a.out,
                      a.out_ld, a.keys, a.label_base, a.n, a.H, a.W, a.label_count, g.band_h,
                      g.strips, g.bands);
   return hipGetLastError();

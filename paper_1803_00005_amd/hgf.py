@@ -26,6 +26,7 @@ HGF_OK, HGF_E_INVALID, HGF_E_NOMEM, HGF_E_DEVICE, HGF_E_UNSUPPORTED, HGF_E_BUSY 
 HGF_F32, HGF_BF16 = 0, 1
 BASIS = {"monomial": 0, "power": 1}
 REG = {"covariance": 0, "ridge": 1}
+STAGES = ["guide_mean", "guide_synth", "guide_moments", "guide_invert", "coef", "out_wta", "wta_keys"]
 
 
 class HGFError(RuntimeError):
@@ -75,6 +76,8 @@ def _declare(lib):
         "hgf_filter_batch": (ctypes.c_int, [_vp, ctypes.c_int32, P, _vp, _vp, _vp, _vp, _vp]),
         "hgf_box_sum": (ctypes.c_int, [_vp, _vp] + [ctypes.c_int32] * 4 + [_vp]),
         "hgf_spd_inverse": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp]),
+        "hgf_set_stage_timing": (ctypes.c_int, [_vp, ctypes.c_int32]),
+        "hgf_stage_times": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
         "hgf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "hgf_last_error": (ctypes.c_char_p, []),
     }
@@ -159,6 +162,18 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # -- per-stage event timing ---------------------------------------------
+    def set_stage_timing(self, enable: bool):
+        _check(lib().hgf_set_stage_timing(self.handle, 1 if enable else 0), "hgf_set_stage_timing")
+
+    def stage_times(self):
+        """{stage name: (milliseconds summed, launches)} since the last call; waits for the events."""
+        n = len(STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int32 * n)()
+        _check(lib().hgf_stage_times(self.handle, ms, cnt, n), "hgf_stage_times")
+        return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
 
     # -- plain path ---------------------------------------------------------
     def filter(self, guide: torch.Tensor, cost: torch.Tensor, *, radius: int, eps: float,
@@ -253,11 +268,13 @@ class Guide:
         return out, best, labels
 
     def export(self, stream=None):
-        """(mu [H][W][n], packed inverse [H][W][D(D+1)/2], shift [n]) as float64 device tensors."""
+        """(mu [H][W][n] float64, packed inverse [H][W][D(D+1)/2] (float32 in the
+        covariance form, float64 in the ridge form), shift [n] float64) as device tensors."""
         H, W = self.shape
         dev = torch.device("cuda", self.ctx.device)
         mu = torch.empty((H, W, self.n), dtype=torch.float64, device=dev)
-        minv = torch.empty((H, W, self.dim * (self.dim + 1) // 2), dtype=torch.float64, device=dev)
+        mdt = torch.float64 if self.params.reg == REG["ridge"] else torch.float32
+        minv = torch.empty((H, W, self.dim * (self.dim + 1) // 2), dtype=mdt, device=dev)
         shift = torch.empty((self.n,), dtype=torch.float64, device=dev)
         _check(lib().hgf_guide_export(self.handle, _ptr(mu), _ptr(minv), _ptr(shift),
                                       _stream(stream)), "hgf_guide_export")

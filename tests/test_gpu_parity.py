@@ -161,7 +161,9 @@ def test_guide_statistics_match_oracle(ctx, w):
                   degree=w.degree, basis=w.basis, reg=reg)
     mu, minv, shift = g.export()
     torch.cuda.synchronize()
-    mu, minv, shift = mu.cpu().numpy(), minv.cpu().numpy(), shift.cpu().numpy()
+    # the covariance form stores the float64 inverse rounded to float32
+    unit = 2.0 ** -24 if minv.dtype == torch.float32 else 2.0 ** -53
+    mu, minv, shift = mu.cpu().numpy(), minv.cpu().numpy().astype(np.float64), shift.cpu().numpy()
     g.close()
     G = O.guidance(guide, w.degree, w.basis)
     n, H, Wd = G.shape
@@ -186,7 +188,7 @@ def test_guide_statistics_match_oracle(ctx, w):
     resid = np.abs(np.einsum("hwij,hwjk->hwik", Mfull, A) - np.eye(D)).max()
     cond = np.linalg.cond(A).max()
     say(f"  max |M A - E| = {resid:.3e}, max cond = {cond:.3e}")
-    assert resid <= 1e-13 * cond * D
+    assert resid <= (1e-13 + 4 * unit) * cond * D
 
 
 def test_two_phase_chunks_equal_plain_path(ctx):
