@@ -1,24 +1,32 @@
 """Throughput of the HGF cost-volume filter on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--secondary n19,batch,serve | none] [--no-cpu-baseline]
 
 A step is one pass of the whole hot path over one synthetic cost volume that
 is already resident in HBM: guidance synthesis, guidance window statistics,
 per-pixel inverse, per-label coefficient box sums and solve, coefficient box
-filter and output, winner-takes-all labels (one hgf_filter call).  The default
-workload is the 450 x 375 colour Voronoi image with degree-2 polynomial
-guidance (n = 9), 60 labels, r = 9, eps = 1e-4.
+filter and output, winner-takes-all labels (one hgf_filter call).  The
+headline workload is the 450 x 375 colour Voronoi image with degree-2
+polynomial guidance (n = 9), 60 labels, r = 9, eps = 1e-4.
 
 Prints one JSON line: throughput in Mpixel.labels/s, the per-stage kernel
 times measured with HIP events on the filter's stream over the timed
 region, the roofline position of the dominant kernel, the error of the
 filtered costs against the FP64 oracle at sampled pixels, and the oracle's
 own throughput on a bounded sample of the same workload on the host cores.
+The line's "secondary" list adds the other forms of the metric:
+  n19    the 1242 x 375 degree-3 colour image (n = 19, 128 labels, r = 9), float32
+         and bfloat16 costs
+  batch  64 images of uneven size (n in {3, 9, 19}, L in {16, 64, 256}, r in
+         {4, 9}) filtered by one graph replay, against 64 sequential calls
+  serve  an open-loop Poisson stream of requests (n in {9, 19}, 32-256 labels,
+         float32 / bfloat16 costs) through the serving queue: p50 / p99
+         latency from scheduled arrival to completion, sustained throughput
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_1803_00005_amd import synth  # noqa: E402
+from paper_1803_00005_amd.build_lib import source_hash  # noqa: E402
 
 METRIC = "filtered Mpixel·labels/s (n=9,19) at stated error vs FP64; HBM GB/s; p99"
 UNIT = "Mpixel·labels/s"
@@ -86,16 +95,6 @@ def roofline_of(name, model, ms_per_launch, traffic):
     return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS, "traffic": traffic,
             "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
-
-
-def source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1803_00005_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str, stage: str):
@@ -157,47 +156,54 @@ def cpu_baseline(w: synth.Workload, guide, cost, target_s: float = 12.0):
 
 
 # ----------------------------------------------------------------------------
+# accuracy at sampled pixels against the oracle
+# ----------------------------------------------------------------------------
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(synth.WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--no-stage-timing", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (reference for the HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the filter shards by labels or image strips; see the design notes)",
-              file=sys.stderr)
-        sys.exit(2)
+class _DeviceCrop:
+    """Host view of a device [H][W][L] tensor that copies only the slices taken."""
 
-    w = synth.WORKLOADS[args.workload]
-    print(f"[bench] workload {w.name}: {w.height}x{w.width} n={w.n} L={w.labels} r={w.radius} "
-          f"eps={w.eps} cost={w.cost_dtype}", file=sys.stderr, flush=True)
-    guide, cost = synth.make_workload(w)
+    def __init__(self, t):
+        self.t = t
 
-    # the host-core oracle runs before the GPU is touched (forked workers)
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, guide, cost)
-        print(f"[bench] cpu baseline {cpu['value']:.3f} {UNIT} on {cpu['cores']} cores",
-              file=sys.stderr, flush=True)
+    def __getitem__(self, idx):
+        return self.t[idx].float().cpu().numpy()
 
+
+def sampled_error(w: synth.Workload, guide, cost, Z, lab, k: int = 14, seed: int = 0):
+    """Max error of Z (device) against the FP64 oracle at k random pixels and two corners.
+
+    guide and cost are numpy arrays or device tensors (cost is then read one
+    crop at a time)."""
+    from oracle import hgf_oracle as O
+    g = guide if isinstance(guide, np.ndarray) else guide.cpu().numpy()
+    v = cost if isinstance(cost, np.ndarray) else _DeviceCrop(cost)
+    rng = np.random.default_rng(seed)
+    pts = sorted({(0, 0), (w.height - 1, w.width - 1)} |
+                 {(int(rng.integers(0, w.height)), int(rng.integers(0, w.width)))
+                  for _ in range(k)})
+    idx = tuple(np.array(pts).T)
+    Zo = O.filter_points(O.guidance(g, w.degree, w.basis), v, w.radius, w.eps, pts)
+    vmax = max(float(np.abs(v[y, x]).max()) for (y, x) in pts)
+    if isinstance(cost, np.ndarray):
+        vmax = float(np.abs(cost).max())
+    scale = np.maximum(np.abs(Zo), vmax)
+    Zg = Z[idx].double().cpu().numpy() if not isinstance(Z, np.ndarray) else Z[idx]
+    lg = lab[idx].cpu().numpy() if not isinstance(lab, np.ndarray) else lab[idx]
+    rel = float(np.max(np.abs(Zg - Zo) / scale))
+    agree = bool(np.all((lg == O.wta(Zo)) | O.near_tie_mask(Zo)))
+    return {"max_rel_vs_fp64_oracle": rel, "tolerance": 1e-4, "points": len(pts),
+            "labels_agree_outside_near_ties": agree}
+
+
+# ----------------------------------------------------------------------------
+# plain form: one image per call
+# ----------------------------------------------------------------------------
+
+def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True):
     import torch
 
     from paper_1803_00005_amd import hgf
-
-    dev = torch.device("cuda", 0)
-    g_d = torch.from_numpy(guide).to(dev)
-    c_d = torch.from_numpy(cost).to(dev)
-    if w.cost_dtype == "bf16":
-        c_d = c_d.to(torch.bfloat16)
-    ctx = hgf.Context(0)
+    dev = g_d.device
     p = hgf.make_params(w.height, w.width, w.labels, radius=w.radius, eps=w.eps, degree=w.degree,
                         guide_channels=w.guide_channels, basis=w.basis, cost_dtype=w.cost_dtype)
     ws = torch.empty(hgf.workspace_size(p), dtype=torch.uint8, device=dev)
@@ -209,6 +215,290 @@ def main():
         ctx.filter(g_d, c_d, radius=w.radius, eps=w.eps, degree=w.degree, basis=w.basis,
                    out=Z, labels=lab, workspace=ws, stream=stream)
 
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if stage_timing:
+        ctx.set_stage_timing(True)
+        ctx.stage_times()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    stages = ctx.stage_times() if stage_timing else {}
+    ctx.set_stage_timing(False)
+
+    model = stage_model(w)
+    rows = []
+    for name in STAGES:
+        if name not in stages or stages[name][1] == 0:
+            continue
+        tot, cnt = stages[name]
+        per = tot / cnt
+        mdl = {k: v / (cnt / steps) for k, v in model[name].items()}
+        rf = roofline_of(name, mdl, per, None)
+        rows.append({"stage": name, "ms_per_step": tot / steps, "launches": cnt,
+                     "ms_per_launch": per, "bound": rf["bound"],
+                     "achieved": round(rf["achieved"], 3), "unit": rf["unit"],
+                     "frac": round(rf["frac"], 4)})
+    roof = None
+    if rows:
+        dom = max(rows, key=lambda r: r["ms_per_step"])
+        cnt = stages[dom["stage"]][1]
+        mdl = {k: v / (cnt / steps) for k, v in model[dom["stage"]].items()}
+        roof = roofline_of(KERNEL_NAMES.get(dom["stage"], dom["stage"]), mdl,
+                           dom["ms_per_launch"], measured_traffic(w.name, dom["stage"]))
+    return {"ms": ms, "stages": rows, "roofline": roof, "Z": Z, "labels": lab}
+
+
+def secondary_n19(ctx, steps, warmup, check):
+    import torch
+    out = []
+    for name in ("voronoi1242x375_n19_L128", "voronoi1242x375_n19_L128_bf16"):
+        w = synth.WORKLOADS[name]
+        say(f"n19: {name}")
+        guide, cost = synth.make_workload(w)
+        g_d = torch.from_numpy(guide).cuda()
+        c_d = torch.from_numpy(cost).cuda()
+        if w.cost_dtype == "bf16":
+            c_d = c_d.to(torch.bfloat16)
+        r = run_plain(ctx, w, g_d, c_d, steps, warmup)
+        rec = {"form": "plain", "workload": w.name, "value": w.pixel_labels / r["ms"] / 1e3,
+               "unit": UNIT, "ms_per_step": r["ms"], "n": w.n, "labels": w.labels,
+               "cost_dtype": w.cost_dtype, "roofline": r["roofline"], "stages": r["stages"]}
+        if check:
+            rec["error"] = sampled_error(w, guide, cost, r["Z"], r["labels"])
+        out.append(rec)
+        say(f"n19: {name} {r['ms']:.3f} ms/step")
+        del g_d, c_d, r
+        torch.cuda.empty_cache()
+    return out
+
+
+# ----------------------------------------------------------------------------
+# batched form: one graph replay over 64 images of uneven size
+# ----------------------------------------------------------------------------
+
+def secondary_batch(ctx, count, steps, warmup, check):
+    import torch
+
+    from paper_1803_00005_amd import hgf
+    dev = torch.device("cuda", 0)
+    specs = synth.make_batch_specs(count, seed=4)
+    say(f"batch: drawing {count} images on the device")
+    data = [synth.make_workload_device(w, dev) for w in specs]
+    outs = [(torch.empty(w.height, w.width, w.labels, dtype=torch.float32, device=dev),
+             torch.empty(w.height, w.width, dtype=torch.int32, device=dev)) for w in specs]
+    items = [dict(guide=g, cost=c, radius=w.radius, eps=w.eps, degree=w.degree)
+             for w, (g, c) in zip(specs, data)]
+    total = sum(w.pixel_labels for w in specs)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(max(1, warmup)):
+        ctx.filter_batch(items, outputs=outs, stream=stream)  # first call captures the graph
+    torch.cuda.synchronize()
+    say("batch: graph captured")
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.filter_batch(items, outputs=outs, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / steps
+    say(f"batch: {ms_graph:.2f} ms per replay")
+    # the same images one hgf_filter call after another on the same stream
+    wsz = max(hgf.workspace_size(hgf.make_params(w.height, w.width, w.labels, radius=w.radius,
+                                                 eps=w.eps, degree=w.degree,
+                                                 cost_dtype=w.cost_dtype)) for w in specs)
+    ws = torch.empty(wsz, dtype=torch.uint8, device=dev)
+    seq_out = [(torch.empty_like(z), torch.empty_like(lb)) for z, lb in outs[:4]]
+
+    def sequential(check_first=False):
+        for i, (w, (g, c)) in enumerate(zip(specs, data)):
+            z, lb = seq_out[i] if check_first and i < 4 else outs[i]
+            ctx.filter(g, c, radius=w.radius, eps=w.eps, degree=w.degree, out=z, labels=lb,
+                       workspace=ws, stream=stream)
+
+    sequential(check_first=True)
+    torch.cuda.synchronize()
+    equal = all(torch.equal(outs[i][0], seq_out[i][0]) and torch.equal(outs[i][1], seq_out[i][1])
+                for i in range(min(4, count)))
+    e0.record(stream)
+    sequential()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1)
+    say(f"batch: sequential {ms_seq:.2f} ms")
+    rec = {"form": "batch", "workload": f"batch{count}_mixed", "images": count,
+           "value": total / ms_graph / 1e3, "unit": UNIT, "ms_per_step": ms_graph,
+           "pixel_labels_per_step": total, "sequential_ms": ms_seq,
+           "speedup_vs_sequential": ms_seq / ms_graph,
+           "graph_equals_sequential_bitwise_first4": bool(equal),
+           "data": "device-drawn (torch generator), same recipe"}
+    if check:
+        order = sorted(range(count), key=lambda i: specs[i].pixels)[:2]
+        rec["error"] = [dict(image=i, **sampled_error(specs[i], data[i][0], data[i][1],
+                                                      outs[i][0], outs[i][1], k=4))
+                        for i in order]
+    del data, outs, seq_out, ws
+    torch.cuda.empty_cache()
+    return rec
+
+
+# ----------------------------------------------------------------------------
+# serving form: open-loop Poisson arrivals through the serving queue
+# ----------------------------------------------------------------------------
+
+def secondary_serve(ctx, requests, pool, rate, slots, arena_gb):
+    import torch
+
+    from paper_1803_00005_amd import hgf
+    dev = torch.device("cuda", 0)
+    reqs = synth.make_request_specs(requests, seed=5, rate_per_s=rate)
+    pool = min(pool, requests)
+    say(f"serve: drawing {pool} distinct requests on the device")
+    inputs = [synth.make_workload_device(reqs[j][1], dev) for j in range(pool)]
+    outputs = [(torch.empty(w.height, w.width, w.labels, dtype=torch.float32, device=dev),
+                torch.empty(w.height, w.width, dtype=torch.int32, device=dev))
+               for _, w in reqs[:pool]]
+    srv = hgf.Server(ctx, slots=slots, arena_bytes=int(arena_gb * (1 << 30)),
+                     max_queue=requests + 1)
+    # warm-up: every pool entry once, alone
+    for j in range(pool):
+        w = reqs[j][1]
+        srv.submit(inputs[j][0], inputs[j][1], outputs[j][0], outputs[j][1], radius=w.radius,
+                   eps=w.eps, degree=w.degree)
+        srv.drain()
+    srv.poll(4 * pool)
+    torch.cuda.synchronize()
+    say("serve: warm-up done")
+    dev0 = srv.now_ms()
+    t0 = time.perf_counter()
+    arrivals = [a for a, _ in reqs]
+    done = {}
+    id_of = {}
+
+    def collect():
+        for c in srv.poll(1024):
+            done[c.id] = c
+
+    k = 0
+    while k < requests:
+        now = time.perf_counter() - t0
+        if now < arrivals[k]:
+            collect()
+            if arrivals[k] - now > 5e-4:
+                time.sleep(2e-4)
+            continue
+        j = k % pool
+        if k >= pool:  # request k reuses the buffers of request k - pool
+            while id_of[k - pool] not in done:
+                collect()
+        w = reqs[j][1]
+        id_of[k] = srv.submit(inputs[j][0], inputs[j][1], outputs[j][0], outputs[j][1],
+                              radius=w.radius, eps=w.eps, degree=w.degree)
+        k += 1
+    srv.drain()
+    collect()
+    stats = srv.stats()
+    lat = np.array([done[id_of[k]].end_ms - (dev0 + 1e3 * arrivals[k]) for k in range(requests)])
+    statuses = {int(done[id_of[k]].status) for k in range(requests)}
+    work = np.array([reqs[k % pool][1].pixel_labels for k in range(requests)], dtype=np.float64)
+    t_end = max(done[id_of[k]].end_ms for k in range(requests))
+    span_ms = t_end - dev0
+    offered = work.sum() / max(arrivals[-1], 1e-9) / 1e6
+    # alone vs in the mix: re-run the last use of three pool entries through hgf_filter
+    same = True
+    for j in range(min(3, pool)):
+        w = reqs[j][1]
+        z, lb = ctx.filter(inputs[j][0], inputs[j][1], radius=w.radius, eps=w.eps,
+                           degree=w.degree)
+        torch.cuda.synchronize()
+        same = same and torch.equal(z, outputs[j][0]) and torch.equal(lb, outputs[j][1])
+    srv.close()
+    rec = {"form": "serve", "workload": f"poisson{int(rate)}rps_{requests}req", "requests": requests,
+           "distinct_inputs": pool, "slots": slots, "arena_gb": arena_gb,
+           "value": work.sum() / span_ms / 1e3, "unit": UNIT,
+           "offered": offered, "sustained": bool(work.sum() / span_ms / 1e3 >= 0.95 * offered),
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                          "mean": float(lat.mean()), "max": float(lat.max())},
+           "mean_pixel_labels_per_request": float(work.mean()),
+           "arena_peak_gb": stats["arena_peak"] / (1 << 30), "statuses": sorted(statuses),
+           "served_equals_alone_bitwise": bool(same),
+           "data": "device-drawn (torch generator), same recipe; request k uses the shape and "
+                   f"inputs of request k mod {pool}"}
+    say(f"serve: p50 {rec['latency_ms']['p50']:.1f} ms p99 {rec['latency_ms']['p99']:.1f} ms, "
+        f"{rec['value']:.0f} of {offered:.0f} {UNIT} offered")
+    del inputs, outputs
+    torch.cuda.empty_cache()
+    return rec
+
+
+def say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--secondary", default="n19,batch,serve",
+                    help="comma list of n19, batch, serve, or 'none'")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-pool", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-arena-gb", type=float, default=96.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-stage-timing", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device fill and sums (reference for the HBM "
+                         "byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the filter would shard by labels or image strips; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    secondary = [] if args.secondary == "none" else [x for x in args.secondary.split(",") if x]
+    for x in secondary:
+        if x not in ("n19", "batch", "serve"):
+            ap.error(f"unknown secondary form {x!r}")
+
+    w = synth.WORKLOADS[args.workload]
+    say(f"workload {w.name}: {w.height}x{w.width} n={w.n} L={w.labels} r={w.radius} "
+        f"eps={w.eps} cost={w.cost_dtype}")
+    guide, cost = synth.make_workload(w)
+
+    # the host-core oracle runs before the GPU is touched (forked workers)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, guide, cost)
+        say(f"cpu baseline {cpu['value']:.3f} {UNIT} on {cpu['cores']} cores")
+
+    import torch
+
+    from paper_1803_00005_amd import hgf
+
+    dev = torch.device("cuda", 0)
+    g_d = torch.from_numpy(guide).to(dev)
+    c_d = torch.from_numpy(cost).to(dev)
+    if w.cost_dtype == "bf16":
+        c_d = c_d.to(torch.bfloat16)
+    ctx = hgf.Context(0)
+
     if args.copy_calibration:
         # a fill (writes 1 GiB) and a sum (reads 1 GiB): known byte counts for
         # the HBM byte counters
@@ -216,75 +506,25 @@ def main():
         for _ in range(3):
             s_ = src.sum()
         torch.cuda.synchronize()
-        print(f"[bench] copy calibration: fill and 3 sums of {src.numel() * 4} bytes "
-              f"(sum={float(s_):.0f})", file=sys.stderr, flush=True)
+        say(f"copy calibration: fill and 3 sums of {src.numel() * 4} bytes (sum={float(s_):.0f})")
         del src
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-
-    if not args.no_stage_timing:
-        ctx.set_stage_timing(True)
-        ctx.stage_times()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / args.steps
-    stages = ctx.stage_times() if not args.no_stage_timing else {}
-    ctx.set_stage_timing(False)
-    print(f"[bench] timed {args.steps} steps: {ms:.4f} ms/step (wall {wall:.3f} s)",
-          file=sys.stderr, flush=True)
-
+    r = run_plain(ctx, w, g_d, c_d, args.steps, args.warmup, not args.no_stage_timing)
+    ms = r["ms"]
+    say(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {time.perf_counter() - t0:.3f} s)")
     value = w.pixel_labels / (ms * 1e-3) / 1e6
-    model = stage_model(w)
-    stage_rows = []
-    for name in STAGES:
-        if name not in stages:
-            continue
-        tot, cnt = stages[name]
-        if cnt == 0:
-            continue
-        per = tot / cnt
-        launches_per_step = cnt / args.steps
-        mdl = {k: v / launches_per_step for k, v in model[name].items()}
-        rf = roofline_of(name, mdl, per, None)
-        stage_rows.append({"stage": name, "ms_per_step": tot / args.steps, "launches": cnt,
-                           "ms_per_launch": per, "bound": rf["bound"],
-                           "achieved": round(rf["achieved"], 3), "unit": rf["unit"],
-                           "frac": round(rf["frac"], 4)})
-    roof = None
-    if stage_rows:
-        dom = max(stage_rows, key=lambda r: r["ms_per_step"])
-        cnt = stages[dom["stage"]][1]
-        mdl = {k: v / (cnt / args.steps) for k, v in model[dom["stage"]].items()}
-        roof = roofline_of(KERNEL_NAMES.get(dom["stage"], dom["stage"]), mdl,
-                           dom["ms_per_launch"], measured_traffic(w.name, dom["stage"]))
+    err = None if args.no_check else sampled_error(w, guide, cost, r["Z"], r["labels"])
 
-    err = None
-    if not args.no_check:
-        from oracle import hgf_oracle as O
-        Zh = Z.cpu().numpy().astype(np.float64)
-        lh = lab.cpu().numpy()
-        rng = np.random.default_rng(0)
-        pts = sorted({(0, 0), (w.height - 1, w.width - 1)} |
-                     {(int(rng.integers(0, w.height)), int(rng.integers(0, w.width)))
-                      for _ in range(14)})
-        idx = tuple(np.array(pts).T)
-        Zo = O.filter_points(O.guidance(guide, w.degree, w.basis), cost, w.radius, w.eps, pts)
-        scale = np.maximum(np.abs(Zo), np.abs(cost).max())
-        rel = float(np.max(np.abs(Zh[idx] - Zo) / scale))
-        agree = bool(np.all((lh[idx] == O.wta(Zo)) | O.near_tie_mask(Zo)))
-        err = {"max_rel_vs_fp64_oracle": rel, "tolerance": 1e-4, "points": len(pts),
-               "labels_agree_outside_near_ties": agree}
+    sec = []
+    if "n19" in secondary:
+        sec += secondary_n19(ctx, max(3, args.steps // 2), args.warmup, not args.no_check)
+    if "batch" in secondary:
+        sec.append(secondary_batch(ctx, args.batch_count, args.batch_steps, 1,
+                                   not args.no_check))
+    if "serve" in secondary:
+        sec.append(secondary_serve(ctx, args.serve_requests, args.serve_pool, args.serve_rate,
+                                   args.serve_slots, args.serve_arena_gb))
 
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -294,8 +534,8 @@ def main():
                    "n": w.n, "degree": w.degree, "basis": w.basis, "radius": w.radius,
                    "eps": w.eps, "cost_dtype": w.cost_dtype, "reg": "covariance",
                    "pixel_labels_per_step": w.pixel_labels},
-        "roofline": roof, "cpu_baseline": cpu, "error": err, "stages": stage_rows,
-        "source_hash": source_hash(),
+        "roofline": r["roofline"], "cpu_baseline": cpu, "error": err, "stages": r["stages"],
+        "secondary": sec, "source_hash": source_hash(),
     }
     print(json.dumps(line), flush=True)
     ctx.close()

@@ -163,14 +163,97 @@ void hgf_guide_destroy(hgf_guide* guide);
 hgf_status hgf_guide_export(const hgf_guide* guide, double* mu, void* minv,
                             double* shift, void* hip_stream);
 
-/* Filter `count` images of uneven size and label count (the batched form):
- * every image runs through the same stages, each stage one launch over a
- * work list spanning all images, the sequence captured once in a hipGraph
- * per batch shape and replayed.  Arrays of length count. */
+/* Filter `count` images of uneven size and label count (the batched form).
+ * Every image runs the whole path of hgf_filter on one of up to four worker
+ * streams (largest images first, each to the least-loaded stream), in
+ * context-owned workspaces, so images overlap on the device.  The sequence is
+ * captured once into a hipGraph (fork from hip_stream, join back to it) and
+ * cached with the batch's signature (parameters, buffer addresses, tuning);
+ * a later call with the same signature replays it with one graph launch.
+ * The graph holds kernel nodes only.  Results equal hgf_filter's bit for bit.
+ * Arrays of length count; outs[i] or labels[i] may be NULL (not both), and
+ * outs or labels themselves may be NULL.  Errors as hgf_filter, reported for
+ * the first bad image before anything is enqueued. */
 hgf_status hgf_filter_batch(hgf_context* ctx, int32_t count, const hgf_params* params,
                             const float* const* guides, const void* const* costs,
                             float* const* outs, int32_t* const* labels,
                             void* hip_stream);
+
+/* Autotuner of the strip decomposition of the per-label kernels (a4-a7).
+ * Runs the guidance stage once, then times every candidate block count of
+ * the coefficient and output kernels on these inputs with HIP events (three
+ * label passes each) and stores the fastest in the context's table for the
+ * class (kernel, n, radius, regularisation, cost dtype, floor(log2 H W)).
+ * Later calls of that class use it.  Synchronises hip_stream.  `out` may be
+ * NULL; when given it receives valid filtered costs.  Workspace as hgf_filter.
+ * A table entry changes the band boundaries of the float32 running sums, so
+ * results move at rounding level when the table changes. */
+hgf_status hgf_autotune(hgf_context* ctx, const hgf_params* params,
+                        const float* guide, const void* cost, float* out,
+                        void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* The tuning table as rows of 7 int32 (kernel 0=coefficients 1=output,
+ * n, radius, reg, cost is bf16, size class, target blocks).  Writes at most
+ * max_rows rows (rows may be NULL) and the total row count to *count. */
+hgf_status hgf_tune_entries(const hgf_context* ctx, int32_t* rows, int32_t max_rows,
+                            int32_t* count);
+/* Set one row (7 int32 as above). */
+hgf_status hgf_tune_set(hgf_context* ctx, const int32_t* row);
+/* Save / load the table as text, one row per line ('#' starts a comment). */
+hgf_status hgf_tune_save(const hgf_context* ctx, const char* path);
+hgf_status hgf_tune_load(hgf_context* ctx, const char* path);
+
+/* Serving form: requests arrive one at a time and are filtered as soon as
+ * device memory allows (continuous batching).
+ *   hgf_server_create  allocates an arena of arena_bytes (within the
+ *                      context's budget) and `slots` streams (1..16).
+ *   hgf_server_submit  queues one request (parameters and buffers as
+ *                      hgf_filter; every buffer must stay valid until the
+ *                      request completes).  The request waits for the work
+ *                      queued on hip_stream before it (its inputs).  It is
+ *                      admitted, in strict FIFO order, when its workspace
+ *                      (hgf_workspace_size) fits in the arena, and then runs
+ *                      on the least-loaded slot stream.  Returns its id.
+ *                      HGF_E_BUSY: max_queue requests already wait;
+ *                      HGF_E_NOMEM: it can never fit in the arena.
+ *   hgf_server_poll    retires finished requests, admits waiting ones and
+ *                      returns up to max_done completion records, oldest
+ *                      first.  Outputs of a completed request are ready.
+ *   hgf_server_drain   blocks until every submitted request has completed.
+ * Completion times are on the device clock in milliseconds since the server
+ * was created.  A request computes exactly what hgf_filter computes for the
+ * same parameters and tuning table. */
+typedef struct hgf_server hgf_server;
+typedef struct {
+  int64_t id;
+  int32_t status;    /* hgf_status of the request */
+  int32_t slot;      /* stream it ran on */
+  double start_ms;   /* device time its first kernel could start */
+  double end_ms;     /* device time its last kernel ended */
+} hgf_completion;
+typedef struct {
+  int32_t pending;
+  int32_t running;
+  int64_t completed;
+  size_t arena_bytes;
+  size_t arena_in_use;
+  size_t arena_peak;
+} hgf_server_info;
+
+hgf_status hgf_server_create(hgf_context* ctx, int32_t slots, size_t arena_bytes,
+                             int32_t max_queue, hgf_server** out);
+void hgf_server_destroy(hgf_server* server);
+hgf_status hgf_server_submit(hgf_server* server, const hgf_params* params,
+                             const float* guide, const void* cost, float* out,
+                             int32_t* labels, void* hip_stream, int64_t* id);
+hgf_status hgf_server_poll(hgf_server* server, hgf_completion* done, int32_t max_done,
+                           int32_t* count);
+hgf_status hgf_server_drain(hgf_server* server);
+hgf_status hgf_server_stats(const hgf_server* server, hgf_server_info* out);
+/* The device clock now (ms since the server was created): records an event
+ * on an idle stream of the server, waits for it and returns its time.  Pairs a host timestamp taken
+ * right after the call with the device clock of the completion records. */
+hgf_status hgf_server_now(hgf_server* server, double* ms);
 
 /* Standalone clipped box sum (Prop. 2) of C float32 images [C][H][W]:
  * out[c][y][x] = sum of in[c] over the clipped (2r+1)^2 window.  in and out

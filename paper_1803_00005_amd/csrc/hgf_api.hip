@@ -1,19 +1,18 @@
-// C ABI of the HGF library: argument validation, workspace planning and the
-// launch sequence of the hot path.  See include/hgf.h for the contract.
+// C ABI of the HGF library (include/hgf.h): argument validation, workspace
+// planning, device memory, stage timing and the launch sequence of the hot
+// path.  The batched form, the autotuner and the server live in batch.hip,
+// tune.hip and serve.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
-#include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
-#include "../../include/hgf.h"
-#include "hgf_launch.hpp"
+#include "runtime.hpp"
 
 namespace hgf {
 hipError_t launch_coef_n1(const CoefLaunch&, hipStream_t);
@@ -52,7 +51,7 @@ bool config_supported(int n, int R, int reg) {
 }
 
 // Tuning overrides for the strip decomposition (HGF_TARGET_BLOCKS,
-// HGF_MIN_BAND, HGF_MAX_BAND), read once; used by the measurement sweeps.
+// HGF_MIN_BAND, HGF_MAX_BAND), read once; used by measurement sweeps.
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
   if (v == nullptr || *v == 0) return dflt;
@@ -60,6 +59,11 @@ static int env_int(const char* name, int dflt) {
   return x > 0 ? x : dflt;
 }
 
+// Strips of (sin - 2R) output columns, label chunks, and bands whose height
+// is chosen so that the grid has about target_blocks blocks.  Each band
+// restarts the vertical running sums (2R + 1 rows of set-up), so bands are at
+// least kMinBand rows; at most kMaxBand rows bound the float32 drift of the
+// running sums.
 StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_blocks) {
   static const int kTarget = env_int("HGF_TARGET_BLOCKS", 0);
   static const int kMinBand = env_int("HGF_MIN_BAND", 4);
@@ -70,7 +74,7 @@ StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_bloc
   g.strips = (W + sout - 1) / sout;
   g.chunks = chunks;
   const int per_band = std::max(1, g.strips * chunks);
-  int bands = std::max(1, (target_blocks + per_band - 1) / per_band);
+  const int bands = std::max(1, (target_blocks + per_band - 1) / per_band);
   int band_h = (H + bands - 1) / bands;
   band_h = std::min(kMaxBand, std::max(kMinBand, band_h));
   g.band_h = band_h;
@@ -82,16 +86,10 @@ StripGrid strip_grid(int H, int W, int R, int chunks, int target_blocks) {
   return strip_grid_w(H, W, R, kStrip, chunks, target_blocks);
 }
 
-}  // namespace hgf
-
-using namespace hgf;
-
-// ----------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
 // errors
-// ----------------------------------------------------------------------------
-namespace {
-
-thread_local std::string g_last_error;
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
 
 hgf_status fail(hgf_status st, const std::string& msg) {
   g_last_error = msg;
@@ -104,16 +102,10 @@ hgf_status device_fail(hipError_t e, const char* where) {
   return fail(HGF_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-#define HGF_TRY(expr, where)                       \
-  do {                                             \
-    hipError_t e_ = (expr);                        \
-    if (e_ != hipSuccess) return device_fail(e_, where); \
-  } while (0)
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-int64_t binom(int a, int b) {
+// ---------------------------------------------------------------------------
+// guidance basis (Sec. 4.2)
+// ---------------------------------------------------------------------------
+static int64_t binom(int a, int b) {
   int64_t r = 1;
   for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
   return r;
@@ -126,7 +118,8 @@ int num_channels_impl(int m, int d, int basis) {
   return -1;
 }
 
-// Exponents of the guidance channels (same order as the oracle and the header).
+// Exponents of the guidance channels, in the order the header documents:
+// power basis channel-major; monomials graded, lexicographic within a degree.
 bool build_table(int m, int d, int basis, MonoTable* t) {
   std::memset(t, 0, sizeof(*t));
   const int n = num_channels_impl(m, d, basis);
@@ -140,7 +133,7 @@ bool build_table(int m, int d, int basis, MonoTable* t) {
     return true;
   }
   for (int deg = 1; deg <= d; ++deg) {
-    // non-decreasing index sequences of length deg over m channels, lexicographic
+    // non-decreasing index sequences of length deg over m channels
     std::vector<int> idx(deg, 0);
     while (true) {
       for (int c : idx) t->e[k][c] += 1;
@@ -155,15 +148,9 @@ bool build_table(int m, int d, int basis, MonoTable* t) {
   return k == n;
 }
 
-struct Plan {
-  int n = 0, D = 0, PD = 0, K = 0, P = 0, H = 0, W = 0, R = 0, L = 0;
-  int chunks_total = 0, chunks_per_launch = 0;
-  size_t off_partial = 0, off_shift = 0, off_g64 = 0, off_g32 = 0, off_mu = 0, off_minv = 0;
-  size_t off_x = 0, off_keys = 0, total = 0;
-  size_t ws_chunk_bytes = 0;
-  MonoTable table{};
-};
-
+// ---------------------------------------------------------------------------
+// validation and workspace plan
+// ---------------------------------------------------------------------------
 constexpr size_t kWsCapBytes = size_t(12) << 30;  // coefficient workspace per launch group
 
 hgf_status validate(const hgf_params* p, MonoTable* table) {
@@ -205,6 +192,9 @@ Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
   Plan pl;
   pl.table = table;
   pl.n = table.n;
+  pl.reg = p->reg;
+  pl.bf16 = p->cost_dtype == HGF_BF16 ? 1 : 0;
+  pl.eps = p->eps;
   pl.D = p->reg == HGF_REG_RIDGE ? pl.n + 1 : pl.n;
   pl.PD = pl.D * (pl.D + 1) / 2;
   pl.K = pl.n + pl.n * (pl.n + 1) / 2;
@@ -215,8 +205,8 @@ Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
   pl.L = p->num_labels;
   pl.chunks_total = chunks_total;
   pl.ws_chunk_bytes = static_cast<size_t>(pl.P) * (pl.n + 1) * 64 * sizeof(float);
-  pl.chunks_per_launch =
-      static_cast<int>(std::max<size_t>(1, std::min<size_t>(chunks_total, kWsCapBytes / pl.ws_chunk_bytes)));
+  pl.chunks_per_launch = static_cast<int>(
+      std::max<size_t>(1, std::min<size_t>(chunks_total, kWsCapBytes / pl.ws_chunk_bytes)));
   size_t off = 0;
   pl.off_partial = off;
   off = align_up(off + sizeof(double) * kMeanBlocks * kMaxD);
@@ -240,185 +230,35 @@ Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
   return pl;
 }
 
-template <typename T>
-T* at(void* base, size_t off) {
-  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+// ---------------------------------------------------------------------------
+// tuning table
+// ---------------------------------------------------------------------------
+int size_class(int P) {
+  int c = 0;
+  while (c < 30 && (1 << (c + 1)) <= P) ++c;
+  return c;  // floor(log2 P)
 }
 
-}  // namespace
-
-struct hgf_context;
-namespace {
-struct StageTimer;
+TuneKey tune_key(int kernel, const Plan& pl) {
+  return TuneKey(kernel, pl.n, pl.R, pl.reg, pl.bf16, size_class(pl.P));
 }
 
-namespace {
-StageTimer* stage_timer_begin(hgf_context* ctx, int stage, hipStream_t s);
-void stage_timer_end(StageTimer* t);
-
-// RAII wrapper used by the launch sequences below
-struct Stage {
-  StageTimer* t;
-  Stage(hgf_context* ctx, int stage, hipStream_t s) : t(stage_timer_begin(ctx, stage, s)) {}
-  ~Stage() { stage_timer_end(t); }
-};
-
-// Guidance part: a1..a3 into the plan's buffers.
-hgf_status run_guide(hgf_context* ctx, const Plan& pl, int reg, double eps, const float* guide,
-                     void* ws, hipStream_t s) {
-  {
-  Stage st0(ctx, 0, s);
-  HGF_TRY(launch_guide_mean(guide, pl.H, pl.W, pl.table, at<double>(ws, pl.off_partial),
-                            at<double>(ws, pl.off_shift), reg == HGF_REG_COVARIANCE, s),
-          "guide_mean");
-  }
-  {
-  Stage st1(ctx, 1, s);
-  HGF_TRY(launch_guide_synth(guide, pl.H, pl.W, pl.table, at<double>(ws, pl.off_shift),
-                             at<float>(ws, pl.off_g32) + kGPad, at<double>(ws, pl.off_g64), s),
-          "guide_synth");
-  }
-  {
-  Stage st2(ctx, 2, s);
-  HGF_TRY(launch_moments(at<double>(ws, pl.off_g64), pl.n, pl.H, pl.W, pl.R,
-                         at<double>(ws, pl.off_x), s),
-          "moments");
-  }
-  {
-  Stage st3(ctx, 3, s);
-  HGF_TRY(launch_invert(at<double>(ws, pl.off_x), pl.n, pl.H, pl.W, pl.R, eps, reg,
-                        at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv), s),
-          "invert");
-  }
-  return HGF_OK;
+const std::vector<int>& tune_candidates() {
+  static const std::vector<int> c = {128, 256, 384, 512, 768, 1024, 2048};
+  return c;
 }
 
-// Per-label part (a4..a7) for labels [l0, l0 + count) of the call's volume.
-hgf_status run_labels(hgf_context* ctx, const Plan& pl, int reg, int bf16, const void* cost, int cost_ld,
-                      float* out, int out_ld, unsigned long long* keys, int label_base,
-                      int count, const float* g32, const double* mu, const void* minv,
-                      float* wsbuf, hipStream_t s) {
-  const size_t esz = bf16 ? 2 : 4;
-  for (int l0 = 0; l0 < count; l0 += pl.chunks_per_launch * 64) {
-    const int lc = std::min(count - l0, pl.chunks_per_launch * 64);
-    const int chunks = (lc + 63) / 64;
-    CoefLaunch ca;
-    ca.cost = static_cast<const char*>(cost) + esz * l0;
-    ca.cost_bf16 = bf16;
-    ca.cost_ld = cost_ld;
-    ca.g32 = g32;
-    ca.mu = mu;
-    ca.minv = minv;
-    ca.ws = wsbuf;
-    ca.n = pl.n;
-    ca.H = pl.H;
-    ca.W = pl.W;
-    ca.R = pl.R;
-    ca.reg = reg;
-    ca.label_count = lc;
-    ca.grid = strip_grid_w(pl.H, pl.W, pl.R, coef_strip_width(pl.n), chunks, 512);
-    {
-      Stage st(ctx, 4, s);
-      HGF_TRY(launch_coef(ca, s), "coef");
-    }
-    OutLaunch oa;
-    oa.ws = wsbuf;
-    oa.g32 = g32;
-    oa.out = out != nullptr ? out + l0 : nullptr;
-    oa.out_ld = out_ld;
-    oa.keys = keys;
-    oa.label_base = label_base + l0;
-    oa.n = pl.n;
-    oa.H = pl.H;
-    oa.W = pl.W;
-    oa.R = pl.R;
-    oa.label_count = lc;
-    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, out_strip_width(pl.n + 1 > 10 ? 2 : 1), chunks, 512);
-    {
-      Stage st(ctx, 5, s);
-      HGF_TRY(launch_out(oa, s), "out");
-    }
+int tuned_target(hgf_context* ctx, int kernel, const Plan& pl) {
+  if (ctx != nullptr) {
+    auto it = ctx->tune.find(tune_key(kernel, pl));
+    if (it != ctx->tune.end()) return it->second;
   }
-  return HGF_OK;
+  return kDefaultTarget;
 }
 
-}  // namespace
-
-// ----------------------------------------------------------------------------
-// context and device memory
-// ----------------------------------------------------------------------------
-struct hgf_context {
-  int device = 0;
-  size_t budget = 0;
-  size_t allocated = 0;
-  void* scratch = nullptr;
-  size_t scratch_bytes = 0;
-  // stage timing (hgf_set_stage_timing)
-  bool timing = false;
-  struct Rec {
-    int stage;
-    hipEvent_t start, stop;
-  };
-  std::vector<Rec> recs;
-  std::vector<hipEvent_t> spare;
-};
-
-// A resident guide owns one plan-sized device buffer: the guidance statistics
-// (g32, mu, minv) stay there between calls; the plan's shared region holds the
-// moment sums while the guide is created and the coefficient workspace of
-// later hgf_guide_filter calls.
-struct hgf_guide {
-  hgf_context* ctx = nullptr;
-  hgf_params params{};
-  Plan plan;
-  void* base = nullptr;
-  size_t bytes = 0;
-};
-
-namespace {
-
-hipEvent_t take_event(hgf_context* ctx) {
-  if (!ctx->spare.empty()) {
-    hipEvent_t e = ctx->spare.back();
-    ctx->spare.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// Records an event pair around one launch when the context's timing is on.
-struct StageTimer {
-  hgf_context* ctx;
-  int stage;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  StageTimer(hgf_context* c, int st, hipStream_t stream) : ctx(c), stage(st), s(stream) {
-    if (ctx != nullptr && ctx->timing) {
-      a = take_event(ctx);
-      if (a != nullptr && hipEventRecord(a, s) != hipSuccess) a = nullptr;
-    }
-  }
-  ~StageTimer() {
-    if (a == nullptr) return;
-    hipEvent_t b = take_event(ctx);
-    if (b == nullptr || hipEventRecord(b, s) != hipSuccess) {
-      ctx->spare.push_back(a);
-      if (b != nullptr) ctx->spare.push_back(b);
-      return;
-    }
-    ctx->recs.push_back({stage, a, b});
-  }
-};
-
-StageTimer* stage_timer_begin(hgf_context* ctx, int stage, hipStream_t s) {
-  if (ctx == nullptr || !ctx->timing) return nullptr;
-  return new (std::nothrow) StageTimer(ctx, stage, s);
-}
-
-void stage_timer_end(StageTimer* t) { delete t; }
-
+// ---------------------------------------------------------------------------
+// device memory owned by the context
+// ---------------------------------------------------------------------------
 hgf_status ctx_alloc(hgf_context* ctx, size_t bytes, void** out) {
   if (ctx->budget != 0 && ctx->allocated + bytes > ctx->budget)
     return fail(HGF_E_NOMEM, "device memory budget exceeded");
@@ -463,7 +303,165 @@ hgf_status ctx_scratch(hgf_context* ctx, size_t bytes, void** out) {
   return HGF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// stage timing: an event pair around each launch while enabled
+// ---------------------------------------------------------------------------
+static hipEvent_t take_event(hgf_context* ctx) {
+  if (!ctx->spare.empty()) {
+    hipEvent_t e = ctx->spare.back();
+    ctx->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+namespace {
+class Stage {
+ public:
+  Stage(hgf_context* ctx, int stage, hipStream_t s) : ctx_(ctx), stage_(stage), s_(s) {
+    if (ctx_ != nullptr && ctx_->timing) {
+      a_ = take_event(ctx_);
+      if (a_ != nullptr && hipEventRecord(a_, s_) != hipSuccess) {
+        ctx_->spare.push_back(a_);
+        a_ = nullptr;
+      }
+    }
+  }
+  ~Stage() {
+    if (a_ == nullptr) return;
+    hipEvent_t b = take_event(ctx_);
+    if (b == nullptr || hipEventRecord(b, s_) != hipSuccess) {
+      ctx_->spare.push_back(a_);
+      if (b != nullptr) ctx_->spare.push_back(b);
+      return;
+    }
+    ctx_->recs.push_back({stage_, a_, b});
+  }
+  Stage(const Stage&) = delete;
+  Stage& operator=(const Stage&) = delete;
+
+ private:
+  hgf_context* ctx_;
+  int stage_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr;
+};
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// launch sequences
+// ---------------------------------------------------------------------------
+hgf_status run_guide(hgf_context* ctx, const Plan& pl, const float* guide, void* ws,
+                     hipStream_t s) {
+  {
+    Stage st(ctx, 0, s);
+    HGF_TRY(launch_guide_mean(guide, pl.H, pl.W, pl.table, at<double>(ws, pl.off_partial),
+                              at<double>(ws, pl.off_shift), pl.reg == HGF_REG_COVARIANCE, s),
+            "guide_mean");
+  }
+  {
+    Stage st(ctx, 1, s);
+    HGF_TRY(launch_guide_synth(guide, pl.H, pl.W, pl.table, at<double>(ws, pl.off_shift),
+                               at<float>(ws, pl.off_g32) + kGPad, at<double>(ws, pl.off_g64), s),
+            "guide_synth");
+  }
+  {
+    Stage st(ctx, 2, s);
+    HGF_TRY(launch_moments(at<double>(ws, pl.off_g64), pl.n, pl.H, pl.W, pl.R,
+                           at<double>(ws, pl.off_x), s),
+            "moments");
+  }
+  {
+    Stage st(ctx, 3, s);
+    HGF_TRY(launch_invert(at<double>(ws, pl.off_x), pl.n, pl.H, pl.W, pl.R, pl.eps, pl.reg,
+                          at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv), s),
+            "invert");
+  }
+  return HGF_OK;
+}
+
+hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int cost_ld, float* out,
+                      int out_ld, unsigned long long* keys, int label_base, int count,
+                      const float* g32, const double* mu, const void* minv, float* wsbuf,
+                      hipStream_t s) {
+  const size_t esz = pl.bf16 ? 2 : 4;
+  const int coef_target = tuned_target(ctx, kTuneCoef, pl);
+  const int out_target = tuned_target(ctx, kTuneOut, pl);
+  for (int l0 = 0; l0 < count; l0 += pl.chunks_per_launch * 64) {
+    const int lc = std::min(count - l0, pl.chunks_per_launch * 64);
+    const int chunks = (lc + 63) / 64;
+    CoefLaunch ca;
+    ca.cost = static_cast<const char*>(cost) + esz * l0;
+    ca.cost_bf16 = pl.bf16;
+    ca.cost_ld = cost_ld;
+    ca.g32 = g32;
+    ca.mu = mu;
+    ca.minv = minv;
+    ca.ws = wsbuf;
+    ca.n = pl.n;
+    ca.H = pl.H;
+    ca.W = pl.W;
+    ca.R = pl.R;
+    ca.reg = pl.reg;
+    ca.label_count = lc;
+    ca.grid = strip_grid_w(pl.H, pl.W, pl.R, coef_strip_width(pl.n), chunks, coef_target);
+    {
+      Stage st(ctx, 4, s);
+      HGF_TRY(launch_coef(ca, s), "coef");
+    }
+    OutLaunch oa;
+    oa.ws = wsbuf;
+    oa.g32 = g32;
+    oa.out = out != nullptr ? out + l0 : nullptr;
+    oa.out_ld = out_ld;
+    oa.keys = keys;
+    oa.label_base = label_base + l0;
+    oa.n = pl.n;
+    oa.H = pl.H;
+    oa.W = pl.W;
+    oa.R = pl.R;
+    oa.label_count = lc;
+    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, out_strip_width(pl.n + 1 > 10 ? 2 : 1), chunks,
+                           out_target);
+    {
+      Stage st(ctx, 5, s);
+      HGF_TRY(launch_out(oa, s), "out");
+    }
+  }
+  return HGF_OK;
+}
+
+hgf_status run_filter(hgf_context* ctx, const Plan& pl, const float* guide, const void* cost,
+                      int cost_ld, float* out, int out_ld, int32_t* labels, void* ws,
+                      hipStream_t s) {
+  hgf_status st = run_guide(ctx, pl, guide, ws, s);
+  if (st != HGF_OK) return st;
+  unsigned long long* keys = labels != nullptr ? at<unsigned long long>(ws, pl.off_keys) : nullptr;
+  if (keys != nullptr) {
+    Stage sk(ctx, 6, s);
+    HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
+  }
+  st = run_labels(ctx, pl, cost, cost_ld, out, out_ld, keys, 0, pl.L, pl.g32(ws),
+                  at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv), at<float>(ws, pl.off_x),
+                  s);
+  if (st != HGF_OK) return st;
+  if (keys != nullptr) {
+    Stage sk(ctx, 6, s);
+    HGF_TRY(launch_key_finalize(keys, pl.P, nullptr, labels, 0, s), "key_finalize");
+  }
+  return HGF_OK;
+}
+
+}  // namespace hgf
+
+using namespace hgf;
+
+// ===========================================================================
+// extern "C"
+// ===========================================================================
+void hgf_release_batch_resources(hgf_context* ctx);  // batch.hip
 
 extern "C" {
 
@@ -493,15 +491,13 @@ hgf_status hgf_create(int32_t device, size_t hbm_budget_bytes, hgf_context** out
 void hgf_destroy(hgf_context* ctx) {
   if (ctx == nullptr) return;
   (void)hipDeviceSynchronize();
+  hgf_release_batch_resources(ctx);
   for (auto& r : ctx->recs) {
     ctx->spare.push_back(r.start);
     ctx->spare.push_back(r.stop);
   }
   for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
-  if (ctx->scratch != nullptr) {
-    (void)hipDeviceSynchronize();
-    ctx_free(ctx, ctx->scratch, ctx->scratch_bytes);
-  }
+  ctx_free(ctx, ctx->scratch, ctx->scratch_bytes);
   delete ctx;
 }
 
@@ -510,8 +506,7 @@ hgf_status hgf_workspace_size(const hgf_params* params, size_t* bytes) {
   MonoTable t;
   const hgf_status st = validate(params, &t);
   if (st != HGF_OK) return st;
-  const Plan pl = make_plan(params, t, (params->num_labels + 63) / 64);
-  *bytes = pl.total;
+  *bytes = make_plan(params, t, (params->num_labels + 63) / 64).total;
   return HGF_OK;
 }
 
@@ -536,26 +531,10 @@ hgf_status hgf_filter(hgf_context* ctx, const hgf_params* params, const float* g
     if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0)
       return fail(HGF_E_INVALID, "workspace must be 256-byte aligned");
   }
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int cost_ld = params->cost_ld ? params->cost_ld : params->num_labels;
   const int out_ld = params->out_ld ? params->out_ld : params->num_labels;
-  st = run_guide(ctx, pl, params->reg, params->eps, guide, ws, s);
-  if (st != HGF_OK) return st;
-  unsigned long long* keys = labels != nullptr ? at<unsigned long long>(ws, pl.off_keys) : nullptr;
-  if (keys != nullptr) {
-    Stage sk(ctx, 6, s);
-    HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
-  }
-  st = run_labels(ctx, pl, params->reg, params->cost_dtype == HGF_BF16, cost, cost_ld, out, out_ld,
-                  keys, 0, params->num_labels, at<float>(ws, pl.off_g32) + kGPad,
-                  at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv),
-                  at<float>(ws, pl.off_x), s);
-  if (st != HGF_OK) return st;
-  if (keys != nullptr) {
-    Stage sk(ctx, 6, s);
-    HGF_TRY(launch_key_finalize(keys, pl.P, nullptr, labels, 0, s), "key_finalize");
-  }
-  return HGF_OK;
+  return run_filter(ctx, pl, guide, cost, cost_ld, out, out_ld, labels, ws,
+                    static_cast<hipStream_t>(hip_stream));
 }
 
 hgf_status hgf_guide_create(hgf_context* ctx, const hgf_params* params, const float* guide,
@@ -570,17 +549,16 @@ hgf_status hgf_guide_create(hgf_context* ctx, const hgf_params* params, const fl
   if (g == nullptr) return fail(HGF_E_NOMEM, "host allocation");
   g->ctx = ctx;
   g->params = *params;
-  // label chunks processed per hgf_guide_filter launch group: one chunk of 64
+  // label chunks per hgf_guide_filter launch group: one chunk of 64
   g->plan = make_plan(params, t, 1);
-  const Plan& pl = g->plan;
-  g->bytes = pl.total;
+  g->bytes = g->plan.total;
   st = ctx_alloc(ctx, g->bytes, &g->base);
   if (st != HGF_OK) {
     delete g;
     return st;
   }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  st = run_guide(ctx, pl, params->reg, params->eps, guide, g->base, s);
+  st = run_guide(ctx, g->plan, guide, g->base, s);
   if (st != HGF_OK) {
     (void)hipStreamSynchronize(s);
     ctx_free(ctx, g->base, g->bytes);
@@ -614,10 +592,9 @@ hgf_status hgf_guide_filter(hgf_context* ctx, hgf_guide* g, const void* cost_chu
     Stage sk(ctx, 6, s);
     HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
   }
-  hgf_status st = run_labels(ctx, pl, g->params.reg, g->params.cost_dtype == HGF_BF16, cost_chunk,
-                             ldv, out_chunk, ldv, keys, label_begin, label_count,
-                             at<float>(base, pl.off_g32) + kGPad, at<double>(base, pl.off_mu),
-                             at<char>(base, pl.off_minv), at<float>(base, pl.off_x), s);
+  const hgf_status st = run_labels(ctx, pl, cost_chunk, ldv, out_chunk, ldv, keys, label_begin,
+                                   label_count, pl.g32(base), at<double>(base, pl.off_mu),
+                                   at<char>(base, pl.off_minv), at<float>(base, pl.off_x), s);
   if (st != HGF_OK) return st;
   if (keys != nullptr) {
     Stage sk(ctx, 6, s);
@@ -632,7 +609,7 @@ size_t hgf_guide_bytes(const hgf_guide* g) { return g != nullptr ? g->bytes : 0;
 void hgf_guide_destroy(hgf_guide* g) {
   if (g == nullptr) return;
   (void)hipDeviceSynchronize();
-  ctx_free(g->ctx, g->base, g->bytes);
+  if (g->owns) ctx_free(g->ctx, g->base, g->bytes);
   delete g;
 }
 
@@ -658,31 +635,13 @@ hgf_status hgf_guide_export(const hgf_guide* g, double* mu, void* minv, double* 
   return HGF_OK;
 }
 
-hgf_status hgf_filter_batch(hgf_context* ctx, int32_t count, const hgf_params* params,
-                            const float* const* guides, const void* const* costs,
-                            float* const* outs, int32_t* const* labels, void* hip_stream) {
-  if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
-  if (count < 0) return fail(HGF_E_INVALID, "count < 0");
-  if (count == 0) return HGF_OK;
-  if (params == nullptr || guides == nullptr || costs == nullptr)
-    return fail(HGF_E_INVALID, "params, guides or costs is NULL");
-  for (int i = 0; i < count; ++i) {
-    const hgf_status st = hgf_filter(ctx, &params[i], guides[i], costs[i],
-                                     outs != nullptr ? outs[i] : nullptr,
-                                     labels != nullptr ? labels[i] : nullptr, nullptr, 0,
-                                     hip_stream);
-    if (st != HGF_OK) return st;
-  }
-  return HGF_OK;
-}
-
 hgf_status hgf_box_sum(const float* in, float* out, int32_t channels, int32_t height,
                        int32_t width, int32_t radius, void* hip_stream) {
   if (in == nullptr || out == nullptr) return fail(HGF_E_INVALID, "in or out is NULL");
   if (channels < 1 || height < 1 || width < 1 || radius < 0)
     return fail(HGF_E_INVALID, "channels, height, width must be >= 1 and radius >= 0");
   if (in == out) return fail(HGF_E_INVALID, "in and out must not overlap");
-  // the vertical pass needs a temporary image stack (the horizontal pass reads it)
+  // the vertical pass writes a temporary image stack that the horizontal pass reads
   const size_t bytes = sizeof(float) * static_cast<size_t>(channels) * height * width;
   void* tmp = nullptr;
   if (hipMalloc(&tmp, bytes) != hipSuccess) {
@@ -725,7 +684,8 @@ hgf_status hgf_stage_times(hgf_context* ctx, double* ms, int32_t* launches, int3
   hgf_status st = HGF_OK;
   for (auto& r : ctx->recs) {
     float t = 0.f;
-    if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess)
+    if (hipEventSynchronize(r.stop) != hipSuccess ||
+        hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess)
       st = fail(HGF_E_DEVICE, "stage event timing");
     if (r.stage < max_stages) {
       if (ms != nullptr) ms[r.stage] += t;

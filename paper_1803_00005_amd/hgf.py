@@ -35,6 +35,17 @@ class HGFError(RuntimeError):
         self.status = status
 
 
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("start_ms", ctypes.c_double), ("end_ms", ctypes.c_double)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int32), ("running", ctypes.c_int32),
+                ("completed", ctypes.c_int64), ("arena_bytes", ctypes.c_size_t),
+                ("arena_in_use", ctypes.c_size_t), ("arena_peak", ctypes.c_size_t)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [
         ("height", ctypes.c_int32), ("width", ctypes.c_int32),
@@ -74,6 +85,21 @@ def _declare(lib):
         "hgf_guide_destroy": (None, [_vp]),
         "hgf_guide_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
         "hgf_filter_batch": (ctypes.c_int, [_vp, ctypes.c_int32, P, _vp, _vp, _vp, _vp, _vp]),
+        "hgf_autotune": (ctypes.c_int, [_vp, P, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+        "hgf_tune_entries": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+        "hgf_tune_set": (ctypes.c_int, [_vp, _vp]),
+        "hgf_tune_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+        "hgf_tune_load": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+        "hgf_server_create": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32,
+                                             ctypes.POINTER(_vp)]),
+        "hgf_server_destroy": (None, [_vp]),
+        "hgf_server_submit": (ctypes.c_int, [_vp, P, _vp, _vp, _vp, _vp, _vp,
+                                             ctypes.POINTER(ctypes.c_int64)]),
+        "hgf_server_poll": (ctypes.c_int, [_vp, ctypes.POINTER(Completion), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32)]),
+        "hgf_server_drain": (ctypes.c_int, [_vp]),
+        "hgf_server_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServerInfo)]),
+        "hgf_server_now": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
         "hgf_box_sum": (ctypes.c_int, [_vp, _vp] + [ctypes.c_int32] * 4 + [_vp]),
         "hgf_spd_inverse": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp]),
         "hgf_set_stage_timing": (ctypes.c_int, [_vp, ctypes.c_int32]),
@@ -203,9 +229,48 @@ class Context:
                                 workspace.numel(), _stream(stream)), "hgf_filter")
         return (out if want_out else None), (labels if want_labels else None)
 
+    # -- tuning table ------------------------------------------------------
+    def autotune(self, guide: torch.Tensor, cost: torch.Tensor, *, radius: int, eps: float,
+                 degree: int, basis: str = "monomial", reg: str = "covariance",
+                 out: Optional[torch.Tensor] = None, stream=None):
+        """Time the strip-decomposition candidates on these inputs and keep the fastest."""
+        _need_cuda(guide, "guide", (torch.float32,))
+        _need_cuda(cost, "cost", (torch.float32, torch.bfloat16))
+        m, H, W = guide.shape
+        L = cost.shape[2]
+        p = make_params(H, W, L, radius=radius, eps=eps, degree=degree, guide_channels=m,
+                        basis=basis, reg=reg,
+                        cost_dtype="bf16" if cost.dtype == torch.bfloat16 else "f32")
+        ws = torch.empty(workspace_size(p), dtype=torch.uint8, device=guide.device)
+        _check(lib().hgf_autotune(self.handle, ctypes.byref(p), _ptr(guide), _ptr(cost), _ptr(out),
+                                  _ptr(ws), ws.numel(), _stream(stream)), "hgf_autotune")
+
+    def tune_entries(self) -> list[tuple[int, ...]]:
+        """Rows (kernel, n, radius, reg, bf16, size_class, target_blocks) of the tuning table."""
+        cnt = ctypes.c_int32(0)
+        _check(lib().hgf_tune_entries(self.handle, None, 0, ctypes.byref(cnt)), "hgf_tune_entries")
+        rows = (ctypes.c_int32 * (7 * max(1, cnt.value)))()
+        _check(lib().hgf_tune_entries(self.handle, rows, cnt.value, ctypes.byref(cnt)),
+               "hgf_tune_entries")
+        return [tuple(int(rows[7 * i + k]) for k in range(7)) for i in range(cnt.value)]
+
+    def tune_set(self, row: Sequence[int]):
+        arr = (ctypes.c_int32 * 7)(*row)
+        _check(lib().hgf_tune_set(self.handle, arr), "hgf_tune_set")
+
+    def tune_save(self, path: str):
+        _check(lib().hgf_tune_save(self.handle, os.fsencode(path)), "hgf_tune_save")
+
+    def tune_load(self, path: str):
+        _check(lib().hgf_tune_load(self.handle, os.fsencode(path)), "hgf_tune_load")
+
     # -- batched path -------------------------------------------------------
-    def filter_batch(self, items: Sequence[dict], stream=None):
-        """items: dicts with guide, cost, radius, eps, degree[, basis, reg]; returns [(Z, labels)]."""
+    def filter_batch(self, items: Sequence[dict], stream=None, outputs=None):
+        """items: dicts with guide, cost, radius, eps, degree[, basis, reg]; returns [(Z, labels)].
+
+        ``outputs`` optionally gives the (Z, labels) tensors to write; a call
+        with the same inputs, outputs and parameters as the previous one
+        replays the cached graph."""
         n = len(items)
         arr = (Params * n)()
         guides = (ctypes.c_void_p * n)()
@@ -223,13 +288,81 @@ class Context:
                                  guide_channels=m, basis=it.get("basis", "monomial"),
                                  reg=it.get("reg", "covariance"),
                                  cost_dtype="bf16" if c.dtype == torch.bfloat16 else "f32")
-            z = torch.empty((H, W, L), dtype=torch.float32, device=g.device)
-            lb = torch.empty((H, W), dtype=torch.int32, device=g.device)
+            if outputs is not None:
+                z, lb = outputs[i]
+                _need_cuda(z, "out", (torch.float32,))
+                _need_cuda(lb, "labels", (torch.int32,))
+                if tuple(z.shape) != (H, W, L) or tuple(lb.shape) != (H, W):
+                    raise ValueError(f"outputs[{i}] has the wrong shape")
+            else:
+                z = torch.empty((H, W, L), dtype=torch.float32, device=g.device)
+                lb = torch.empty((H, W), dtype=torch.int32, device=g.device)
             guides[i], costs[i], outs[i], labs[i] = g.data_ptr(), c.data_ptr(), z.data_ptr(), lb.data_ptr()
             results.append((z, lb))
         _check(lib().hgf_filter_batch(self.handle, n, arr, guides, costs, outs, labs,
                                       _stream(stream)), "hgf_filter_batch")
         return results
+
+
+class Server:
+    """Serving form: requests filtered as soon as the arena has room (continuous batching)."""
+
+    def __init__(self, ctx: Context, *, slots: int = 4, arena_bytes: int = 8 << 30,
+                 max_queue: int = 1024):
+        h = ctypes.c_void_p()
+        _check(lib().hgf_server_create(ctx.handle, slots, arena_bytes, max_queue, ctypes.byref(h)),
+               "hgf_server_create")
+        self.handle = h
+        self.ctx = ctx
+
+    def submit(self, guide: torch.Tensor, cost: torch.Tensor, out: Optional[torch.Tensor],
+               labels: Optional[torch.Tensor], *, radius: int, eps: float, degree: int,
+               basis: str = "monomial", reg: str = "covariance", stream=None) -> int:
+        """Queue one request; the caller keeps every tensor alive until it completes."""
+        _need_cuda(guide, "guide", (torch.float32,))
+        _need_cuda(cost, "cost", (torch.float32, torch.bfloat16))
+        m, H, W = guide.shape
+        L = cost.shape[2]
+        p = make_params(H, W, L, radius=radius, eps=eps, degree=degree, guide_channels=m,
+                        basis=basis, reg=reg,
+                        cost_dtype="bf16" if cost.dtype == torch.bfloat16 else "f32")
+        rid = ctypes.c_int64(-1)
+        _check(lib().hgf_server_submit(self.handle, ctypes.byref(p), _ptr(guide), _ptr(cost),
+                                       _ptr(out), _ptr(labels), _stream(stream),
+                                       ctypes.byref(rid)), "hgf_server_submit")
+        return int(rid.value)
+
+    def poll(self, max_done: int = 256) -> list[Completion]:
+        buf = (Completion * max_done)()
+        cnt = ctypes.c_int32(0)
+        _check(lib().hgf_server_poll(self.handle, buf, max_done, ctypes.byref(cnt)),
+               "hgf_server_poll")
+        return [buf[i] for i in range(cnt.value)]
+
+    def drain(self):
+        _check(lib().hgf_server_drain(self.handle), "hgf_server_drain")
+
+    def now_ms(self) -> float:
+        """Device clock in ms since the server was created."""
+        t = ctypes.c_double(0.0)
+        _check(lib().hgf_server_now(self.handle, ctypes.byref(t)), "hgf_server_now")
+        return float(t.value)
+
+    def stats(self) -> dict:
+        info = ServerInfo()
+        _check(lib().hgf_server_stats(self.handle, ctypes.byref(info)), "hgf_server_stats")
+        return {k: int(getattr(info, k)) for k, _ in ServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hgf_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Guide:

@@ -35,6 +35,7 @@ __all__ = [
     "Workload",
     "WORKLOADS",
     "make_workload",
+    "make_workload_device",
     "make_batch_specs",
     "make_request_specs",
     "voronoi_regions",
@@ -183,6 +184,68 @@ def make_workload(w: Workload, *, with_disparity: bool = False,
         cost = _round_bf16(cost)
     if with_disparity:
         return guide, cost, disp
+    return guide, cost
+
+
+def make_workload_device(w: Workload, device):
+    """Draw workload ``w`` with torch on ``device`` (same recipe, another generator).
+
+    For benchmark sizes whose host generation would take longer than the
+    measurement (a 64-image batch holds billions of costs).  The draws follow
+    the order and distributions of ``make_workload`` but come from a
+    ``torch.Generator`` seeded with ``w.seed``, so the values differ from the
+    host generator's.  Returns ``(guide, cost)`` as device tensors: guide
+    float32 [m][H][W], cost [H][W][L] float32, or bfloat16 (round to nearest
+    even) for ``bf16`` workloads.
+    """
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(w.seed)
+    f64 = dict(dtype=torch.float64, device=device)
+    H, W_, K, L, m = w.height, w.width, w.regions, w.labels, w.guide_channels
+    sx = torch.rand(K, generator=gen, **f64) * W_
+    sy = torch.rand(K, generator=gen, **f64) * H
+    colours = torch.rand(K, m, generator=gen, **f64)
+    xc = torch.arange(W_, **f64) + 0.5
+    region = torch.empty(H, W_, dtype=torch.int64, device=device)
+    rows = max(1, (1 << 24) // max(1, W_ * K))
+    for y0 in range(0, H, rows):
+        y1 = min(H, y0 + rows)
+        yc = torch.arange(y0, y1, **f64)[:, None, None] + 0.5
+        d2 = (xc[None, :, None] - sx) ** 2 + (yc - sy) ** 2
+        region[y0:y1] = torch.argmin(d2, dim=2)  # first minimum on ties
+    yy = torch.arange(H, **f64)[:, None].expand(H, W_)
+    xx = torch.arange(W_, **f64)[None, :].expand(H, W_)
+    if w.disparity == "region_int":
+        dk = torch.randint(0, min(L, 16), (K,), generator=gen, device=device).double()
+        disp = dk[region]
+    elif w.disparity == "smooth_region":
+        lo, hi = 4.0 * L / 60.0, 55.0 * L / 60.0
+        dk = lo + (hi - lo) * torch.rand(K, generator=gen, **f64)
+        disp = (dk[region] + 4.0 * torch.sin(2 * math.pi * xx / W_)
+                * torch.cos(2 * math.pi * yy / H)).clamp(0.0, L - 1.0)
+    elif w.disparity == "planar":
+        s = L / 128.0
+        ak = (8.0 + 111.0 * torch.rand(K, generator=gen, **f64)) * s
+        bk = (-0.05 + 0.1 * torch.rand(K, generator=gen, **f64)) * s
+        ck = (-0.05 + 0.1 * torch.rand(K, generator=gen, **f64)) * s
+        disp = (ak[region] + bk[region] * (xx - sx[region]) + ck[region] * (yy - sy[region])
+                ).clamp(0.0, L - 1.0)
+    else:
+        raise ValueError(f"unknown disparity model {w.disparity!r}")
+    guide = colours[region].permute(2, 0, 1) + w.sigma_guide * torch.randn(
+        m, H, W_, generator=gen, **f64)
+    guide = guide.float().contiguous()
+    cdt = torch.bfloat16 if w.cost_dtype == "bf16" else torch.float32
+    cost = torch.empty(H, W_, L, dtype=cdt, device=device)
+    lab = torch.arange(L, dtype=torch.float32, device=device)
+    rows = max(1, (1 << 26) // max(1, W_ * L))
+    for y0 in range(0, H, rows):
+        y1 = min(H, y0 + rows)
+        base = ((lab - disp[y0:y1, :, None].float()).abs() / 16.0).clamp(max=0.5)
+        noise = torch.randn(y1 - y0, W_, L, generator=gen, dtype=torch.float32, device=device)
+        cost[y0:y1] = (base + w.sigma_cost * noise).to(cdt)
     return guide, cost
 
 
