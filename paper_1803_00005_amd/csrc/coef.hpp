@@ -13,14 +13,17 @@
 // pixel.  Everything per-pixel (M_p, mu_p, G(p), N_p) is wave-uniform and is
 // read with scalar loads into SGPRs, so the n x n times n x 64 product runs
 // as plain VALU FMAs with one scalar operand and no operand traffic.
-// A workgroup owns a strip of 64 state columns (64 - 2R output columns) over a
-// band of rows.  Its waves split the n + 1 product channels: each wave keeps
-// float32 vertical running sums of its channels for all 64 columns in
+// A workgroup owns a strip of SIN state columns (SIN - 2R output columns) over
+// a band of rows.  Its waves split the n + 1 product channels: each wave keeps
+// float32 vertical running sums of its channels for all state columns in
 // registers (add the row entering the window, subtract the row leaving it)
 // and forms the horizontal window sums in registers with float64 running
 // sums, so the only shared-memory traffic is one transpose of the finished
-// window sums T, U per output pixel before the solve.  Bands restart the
-// vertical sums, which bounds float32 drift to band_h + 2R additions.
+// window sums T, U of a row before the solves.  Bands restart the vertical
+// sums, which bounds float32 drift to band_h + 2R additions.
+//
+// Strips inside the image take a path without column bounds handling; the two
+// border strips clamp their addresses and weight out-of-image columns by zero.
 #pragma once
 
 #include <type_traits>
@@ -28,12 +31,91 @@
 #include "hgf_launch.hpp"
 
 namespace hgf {
+// LDS for the transposed window sums of one row chunk: with up to ten
+// channels one chunk holds the whole row; above, smaller chunks measured
+// faster (the solves of a chunk start sooner).
+constexpr int coef_lds_bytes(int nch) { return nch <= 10 ? 120 * 1024 : 50 * 1024; }
 
-template <int R, int CPW, int NG, int RIDGE, typename TIN, int SIN>
-__global__ __launch_bounds__(640) void coef_kernel(
-    const TIN* __restrict__ cost, int cost_ld, const float* __restrict__ g32,
-    const double* __restrict__ mu, const void* __restrict__ minv_void, float* __restrict__ ws,
-    int H, int W, int label_count, int band_h, int strips, int bands) {
+template <int NCH, int SOUT>
+constexpr int coef_column_chunk() {
+  int oc = coef_lds_bytes(NCH) / (NCH * 64 * 4);
+  if (oc > SOUT) oc = SOUT;
+  if (oc < 1) oc = 1;
+  const int ncb = (SOUT + oc - 1) / oc;
+  return (SOUT + ncb - 1) / ncb;  // balanced chunks
+}
+
+// One vertical window update of every state column: SIGN (+1 or -1) times
+// the products G_ch * Y of row yy.
+template <int SIGN, bool CHECK, int CPW, int NCH, int SIN, typename TIN>
+__device__ __forceinline__ void coef_vrow(float (&vs)[CPW][SIN], const TIN* __restrict__ cost,
+                                          int cost_ld, const float* __restrict__ g32, size_t P,
+                                          int yy, int xsl, int W, int labc, int wv) {
+  const TIN* __restrict__ crow = cost + static_cast<size_t>(yy) * W * cost_ld;
+  const float* __restrict__ grow = g32 + static_cast<size_t>(yy) * W + xsl;
+#pragma unroll
+  for (int c0 = 0; c0 < SIN; c0 += kGrp) {
+    float yv[kGrp];
+#pragma unroll
+    for (int c = 0; c < kGrp; ++c) {
+      if (c0 + c < SIN) {
+        const int xr = xsl + c0 + c;
+        const int xc = CHECK ? min(max(xr, 0), W - 1) : xr;
+        yv[c] = load_cost<TIN>(crow, static_cast<uint32_t>(xc) * static_cast<uint32_t>(cost_ld) + labc);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      const int ch = wv * CPW + k;
+      const int chc = (NCH % CPW == 0) ? ch : min(ch, NCH - 1);
+      const float* __restrict__ gp = grow + static_cast<size_t>(chc) * P + c0;
+#pragma unroll
+      for (int c = 0; c < kGrp; ++c) {
+        if (c0 + c < SIN) {
+          const int xr = xsl + c0 + c;
+          const bool ok = ((NCH % CPW == 0) || ch < NCH) && (!CHECK || (xr >= 0 && xr < W));
+          const float g = ldu(gp, c);
+          vs[k][c0 + c] = fmaf(ok ? (SIGN > 0 ? g : -g) : 0.f, yv[c], vs[k][c0 + c]);
+        }
+      }
+    }
+  }
+}
+
+// Copy `dwords` consecutive dwords from global memory into LDS without
+// passing through registers (global_load_lds, asynchronous: the copy is
+// complete after the issuing wave's vmcnt reaches zero, visible to the other
+// waves after the next barrier).  Lanes past the end re-read the last dword
+// into the padding of the LDS buffer, so no lane reads outside the source.
+template <int NW>
+__device__ __forceinline__ void stage_dwords(const uint32_t* __restrict__ src,
+                                             uint32_t* __restrict__ dst, int dwords, int wv,
+                                             int lane) {
+  for (int base = wv * 64; base < dwords; base += NW * 64) {
+    const int i = min(base + lane, dwords - 1);
+    __builtin_amdgcn_global_load_lds(src + i, dst + base, 4, 0, 0);
+  }
+}
+
+// Dwords of LDS for the inverses and window means of one row of a strip,
+// rounded up to whole waves.
+template <int SOUT, int NG, int RIDGE>
+constexpr int coef_stage_dwords() {
+  constexpr int D = RIDGE ? NG + 1 : NG;
+  constexpr int PD = D * (D + 1) / 2;
+  constexpr int m = SOUT * PD * (RIDGE ? 2 : 1);
+  constexpr int u = RIDGE ? 0 : SOUT * NG * 2;
+  return (m + 63) / 64 * 64 + (u + 63) / 64 * 64;
+}
+
+template <int R, int CPW, int NG, int RIDGE, typename TIN, int SIN, bool CHECK>
+__device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cost_ld,
+                                           const float* __restrict__ g32,
+                                           const double* __restrict__ mu,
+                                           const void* __restrict__ minv_void,
+                                           float* __restrict__ wsc, int H, int W, int xs,
+                                           int x_out0, int y0, int y1, int labc, int wv, int lane,
+                                           float* __restrict__ lds, uint32_t* __restrict__ stage) {
   constexpr int SOUT = SIN - 2 * R;
   constexpr int NCH = NG + 1;
   constexpr int NW = (NCH + CPW - 1) / CPW;
@@ -41,34 +123,11 @@ __global__ __launch_bounds__(640) void coef_kernel(
   constexpr int PD = D * (D + 1) / 2;
   using MT = typename std::conditional<RIDGE != 0, double, float>::type;
   const MT* __restrict__ minv = static_cast<const MT*>(minv_void);
-  // scalar loads of M are issued in blocks of this many elements (SMEM returns
-  // out of order, so a block is waited for as a whole)
-  constexpr int MBLK = RIDGE ? 32 : 64;
-  constexpr int OC_RAW = 12800 / (NCH * 64);
-  constexpr int OC = OC_RAW < 1 ? 1 : (OC_RAW > SOUT ? SOUT : OC_RAW);
-  __shared__ float lds[OC * NCH * 64];
-
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // work item of this block; integer division runs on the vector ALU, so the
-  // results are moved back to scalar registers explicitly
-  // logical order: label chunk fastest, then strip, then band (one XCD gets a
-  // contiguous range, so both label chunks of a strip share the L2 copy of M)
-  int bid = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
-  const int chunks = __builtin_amdgcn_readfirstlane(static_cast<int>(gridDim.x) / (strips * bands));
-  const int chunk = __builtin_amdgcn_readfirstlane(bid % chunks);
-  bid = __builtin_amdgcn_readfirstlane(bid / chunks);
-  const int strip = __builtin_amdgcn_readfirstlane(bid % strips);
-  const int band = __builtin_amdgcn_readfirstlane(bid / strips);
-  const int x_out0 = strip * SOUT;
-  const int xs = x_out0 - R;
-  const int y0 = band * band_h;
-  const int y1 = min(H, y0 + band_h);
-  const int lab = chunk * 64 + lane;
-  // lanes past the last label read the last label's costs; their results are never used
-  const int labc = min(lab, label_count - 1);
+  // inverse elements read from LDS per scheduling block of the product
+  constexpr int MBLK = RIDGE ? 8 : 16;
+  constexpr int OC = coef_column_chunk<NCH, SOUT>();
+  constexpr int NCB = (SOUT + OC - 1) / OC;
   const size_t P = static_cast<size_t>(H) * W;
-  float* __restrict__ wsc = ws + static_cast<size_t>(chunk) * P * NCH * 64;
 
   float vs[CPW][SIN];
 #pragma unroll
@@ -76,55 +135,27 @@ __global__ __launch_bounds__(640) void coef_kernel(
 #pragma unroll
     for (int c = 0; c < SIN; ++c) vs[k][c] = 0.f;
 
-  // Vertical update with row yy for all state columns, in groups of kGrp
-  // columns whose loads are all issued before they are used.  Columns outside
-  // the image read a clamped pixel (costs) or padding (guidance) and get weight
-  // 0 by a wave-uniform select.  The strip origin is laundered so that the
-  // per-column offsets are recomputed for each row rather than hoisted out of
-  // the row loop (64 live offsets would spill).
-  const size_t Pp = P;
-  auto acc_row = [&](int yy, bool add) {
+  // The strip origin is laundered so that the per-column offsets are
+  // recomputed for each row rather than hoisted out of the row loop (64 live
+  // offsets would spill).
+  auto launder = [&]() {
     int xsl = __builtin_amdgcn_readfirstlane(xs);
     asm volatile("" : "+s"(xsl));
-    xsl = __builtin_amdgcn_readfirstlane(xsl);
-    const TIN* __restrict__ crow = cost + static_cast<size_t>(yy) * W * cost_ld;
-    const float* __restrict__ grow = g32 + static_cast<size_t>(yy) * W + xsl;
-#pragma unroll
-    for (int c0 = 0; c0 < SIN; c0 += kGrp) {
-      constexpr int G0 = kGrp;
-      float yv[G0];
-#pragma unroll
-      for (int c = 0; c < G0; ++c) {
-        if (c0 + c < SIN) {
-          const int xc = min(max(xsl + c0 + c, 0), W - 1);
-          yv[c] = load_cost<TIN>(crow, static_cast<uint32_t>(xc) * static_cast<uint32_t>(cost_ld) + labc);
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < CPW; ++k) {
-        const int ch = wv * CPW + k;
-        const int chc = ch < NCH ? ch : NCH - 1;
-        const float* __restrict__ gp = grow + static_cast<size_t>(chc) * Pp + c0;
-#pragma unroll
-        for (int c = 0; c < G0; ++c) {
-          if (c0 + c < SIN) {
-            const int xr = xsl + c0 + c;
-            const float g = ldu(gp, c);
-            const bool ok = xr >= 0 && xr < W && ch < NCH;
-            const float gw = ok ? (add ? g : -g) : 0.f;
-            vs[k][c0 + c] = fmaf(gw, yv[c], vs[k][c0 + c]);
-          }
-        }
-      }
-    }
+    return __builtin_amdgcn_readfirstlane(xsl);
   };
 
-  auto solve_store = [&](int x, int y, int q) {
+  // this row's inverses [SOUT][PD] and (covariance form) window means
+  // [SOUT][NG], staged in LDS at the start of the row step
+  constexpr int M_DWORDS = SOUT * PD * (RIDGE ? 2 : 1);
+  const MT* __restrict__ sm = reinterpret_cast<const MT*>(stage);
+  const double* __restrict__ su = reinterpret_cast<const double*>(stage + (M_DWORDS + 63) / 64 * 64);
+
+  auto solve_store = [&](int x, int y, int q, int qx) {
     const size_t p = static_cast<size_t>(y) * W + x;
     float T[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) T[ch] = lds[(q * NCH + ch) * 64 + lane];
-    const MT* __restrict__ mp = minv + p * PD;
+    const MT* __restrict__ mp = sm + qx * PD;
     float* __restrict__ o = wsc + p * NCH * 64 + lane;
     if (!RIDGE) {
       // c = (T - mu U) / N in float64, then the product a = M c in float32
@@ -134,7 +165,7 @@ __global__ __launch_bounds__(640) void coef_kernel(
       float av[NG];
 #pragma unroll
       for (int i = 0; i < NG; ++i) {
-        c[i] = static_cast<float>((static_cast<double>(T[i + 1]) - ldu(mu, p * NG + i) * U) * invN);
+        c[i] = static_cast<float>((static_cast<double>(T[i + 1]) - su[qx * NG + i] * U) * invN);
         av[i] = 0.f;
       }
 #pragma unroll
@@ -142,22 +173,17 @@ __global__ __launch_bounds__(640) void coef_kernel(
 #pragma unroll
         for (int j = i; j < NG; ++j) {
           const int qq = packed_index(i, j, D);
+          // bound the LDS reads in flight (each holds a register)
           if (qq % MBLK == 0) __builtin_amdgcn_sched_barrier(0);
-          const float m = static_cast<float>(ldu(mp, qq));
+          const float m = static_cast<float>(mp[qq]);
           av[i] = fmaf(m, c[j], av[i]);
           if (j != i) av[j] = fmaf(m, c[i], av[j]);
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
-      // intercept b = U / N - a . mu in float64; mu is read again (not kept
-      // live across the product, whose M block needs the scalar registers)
-      int pl = __builtin_amdgcn_readfirstlane(static_cast<int>(p));
-      asm volatile("" : "+s"(pl));
-      pl = __builtin_amdgcn_readfirstlane(pl);
+      // intercept b = U / N - a . mu in float64
       double b = U * invN;
 #pragma unroll
-      for (int i = 0; i < NG; ++i)
-        b = fma(-static_cast<double>(av[i]), ldu(mu, static_cast<size_t>(pl) * NG + i), b);
+      for (int i = 0; i < NG; ++i) b = fma(-static_cast<double>(av[i]), su[qx * NG + i], b);
       o[0] = static_cast<float>(b);
 #pragma unroll
       for (int i = 0; i < NG; ++i) o[(i + 1) * 64] = av[i];
@@ -175,7 +201,7 @@ __global__ __launch_bounds__(640) void coef_kernel(
         for (int j = i; j < D; ++j) {
           const int qq = packed_index(i, j, D);
           if (qq % MBLK == 0) __builtin_amdgcn_sched_barrier(0);
-          const double m = static_cast<double>(ldu(mp, qq));
+          const double m = static_cast<double>(mp[qq]);
           w[i] = fma(m, v[j], w[i]);
           if (j != i) w[j] = fma(m, v[i], w[j]);
         }
@@ -185,25 +211,32 @@ __global__ __launch_bounds__(640) void coef_kernel(
     }
   };
 
-  // Warm the L2 with the inverses of this row's output pixels (one vector
-  // load touching each of their cache lines), so the scalar loads of the
-  // product later hit L2 instead of HBM.
-  auto prefetch_minv = [&](int y) -> float {
-    constexpr int LINE_ELEMS = 128 / sizeof(MT);
-    const size_t first = (static_cast<size_t>(y) * W + x_out0) * PD;
-    const size_t total = static_cast<size_t>(min(SOUT, W - x_out0)) * PD;
-    const size_t e = static_cast<size_t>(lane + 64 * wv) * LINE_ELEMS;
-    return e < total ? static_cast<float>(minv[first + e]) : 0.f;
+  // Stage the inverses and means of row y's output pixels into LDS.  Issued
+  // before the row's vertical update so the copy overlaps it; the barrier
+  // before the solves makes it visible (the previous row's solves are past
+  // their closing barrier, so the buffer is free).
+  auto stage_row = [&](int y) {
+    const int cnt = min(SOUT, W - x_out0);
+    const size_t p0 = static_cast<size_t>(y) * W + x_out0;
+    stage_dwords<NW>(reinterpret_cast<const uint32_t*>(minv + p0 * PD), stage,
+                     cnt * PD * (RIDGE ? 2 : 1), wv, lane);
+    if (!RIDGE)
+      stage_dwords<NW>(reinterpret_cast<const uint32_t*>(mu + p0 * NG),
+                       stage + (M_DWORDS + 63) / 64 * 64, cnt * NG * 2, wv, lane);
   };
 
-  for (int yy = max(0, y0 - R); yy <= min(H - 1, y0 + R); ++yy) acc_row(yy, true);
+  for (int yy = max(0, y0 - R); yy <= min(H - 1, y0 + R); ++yy)
+    coef_vrow<1, CHECK, CPW, NCH, SIN, TIN>(vs, cost, cost_ld, g32, P, yy, launder(), W, labc, wv);
   for (int y = y0; y < y1; ++y) {
-    const float pf = prefetch_minv(y);
+    stage_row(y);
     if (y > y0) {
-      if (y + R < H) acc_row(y + R, true);
-      if (y - R - 1 >= 0) acc_row(y - R - 1, false);
+      if (y + R < H)
+        coef_vrow<1, CHECK, CPW, NCH, SIN, TIN>(vs, cost, cost_ld, g32, P, y + R, launder(), W,
+                                               labc, wv);
+      if (y - R - 1 >= 0)
+        coef_vrow<-1, CHECK, CPW, NCH, SIN, TIN>(vs, cost, cost_ld, g32, P, y - R - 1, launder(),
+                                                W, labc, wv);
     }
-    asm volatile("" ::"v"(pf));
     double hs[CPW];
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
@@ -214,7 +247,6 @@ __global__ __launch_bounds__(640) void coef_kernel(
     // Output columns in LDS-sized chunks: the unrolled part touches only the
     // register state (horizontal sums -> LDS); the solve runs after it as an
     // ordinary loop, so the state array stays in registers.
-    constexpr int NCB = (SOUT + OC - 1) / OC;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
 #pragma unroll
@@ -238,15 +270,57 @@ __global__ __launch_bounds__(640) void coef_kernel(
           }
         }
       }
+      // the staged row must have landed before the barrier publishes it
+      if (cb == 0) __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       const int cnt = min(OC, SOUT - cb * OC);
       for (int q = wv; q < cnt; q += NW) {
         const int x = x_out0 + cb * OC + q;
-        if (x < W) solve_store(x, y, q);
+        if (x < W) solve_store(x, y, q, cb * OC + q);
       }
       __syncthreads();
     }
   }
+}
+
+template <int R, int CPW, int NG, int RIDGE, typename TIN, int SIN>
+__global__ __launch_bounds__(640) void coef_kernel(
+    const TIN* __restrict__ cost, int cost_ld, const float* __restrict__ g32,
+    const double* __restrict__ mu, const void* __restrict__ minv, float* __restrict__ ws,
+    int H, int W, int label_count, int band_h, int strips, int bands) {
+  constexpr int SOUT = SIN - 2 * R;
+  constexpr int NCH = NG + 1;
+  constexpr int OC = coef_column_chunk<NCH, SOUT>();
+  __shared__ float lds[OC * NCH * 64];
+  __shared__ uint32_t stage[coef_stage_dwords<SOUT, NG, RIDGE>()];
+
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // work item of this block; integer division runs on the vector ALU, so the
+  // results are moved back to scalar registers explicitly
+  // logical order: label chunk fastest, then strip, then band (one XCD gets a
+  // contiguous range, so both label chunks of a strip share the L2 copy of M)
+  int bid = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int chunks = __builtin_amdgcn_readfirstlane(static_cast<int>(gridDim.x) / (strips * bands));
+  const int chunk = __builtin_amdgcn_readfirstlane(bid % chunks);
+  bid = __builtin_amdgcn_readfirstlane(bid / chunks);
+  const int strip = __builtin_amdgcn_readfirstlane(bid % strips);
+  const int band = __builtin_amdgcn_readfirstlane(bid / strips);
+  const int x_out0 = strip * SOUT;
+  const int xs = x_out0 - R;
+  const int y0 = band * band_h;
+  const int y1 = min(H, y0 + band_h);
+  const int lab = chunk * 64 + lane;
+  // lanes past the last label read the last label's costs; their results are never used
+  const int labc = min(lab, label_count - 1);
+  const size_t P = static_cast<size_t>(H) * W;
+  float* __restrict__ wsc = ws + static_cast<size_t>(chunk) * P * NCH * 64;
+  if (xs >= 0 && xs + SIN <= W)
+    coef_strip<R, CPW, NG, RIDGE, TIN, SIN, false>(cost, cost_ld, g32, mu, minv, wsc, H, W, xs,
+                                                   x_out0, y0, y1, labc, wv, lane, lds, stage);
+  else
+    coef_strip<R, CPW, NG, RIDGE, TIN, SIN, true>(cost, cost_ld, g32, mu, minv, wsc, H, W, xs,
+                                                  x_out0, y0, y1, labc, wv, lane, lds, stage);
 }
 
 template <int R, int NG, int RIDGE, typename TIN>

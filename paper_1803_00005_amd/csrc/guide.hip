@@ -26,9 +26,16 @@ __device__ __forceinline__ double monomial(const MonoTable& t, int k, const floa
 // guidance.  Each block reduces a fixed pixel subset in a fixed order, so the
 // result does not depend on scheduling.
 // ---------------------------------------------------------------------------
+// Sum over the 64 lanes of a wave by a fixed butterfly (deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __global__ __launch_bounds__(256) void guide_mean_partial_kernel(
     const float* __restrict__ I, int P, MonoTable t, double* __restrict__ partial) {
-  __shared__ double red[256];
+  __shared__ double red[4][kMaxD];
   double acc[kMaxD];
 #pragma unroll
   for (int k = 0; k < kMaxD; ++k) acc[k] = 0.0;
@@ -39,36 +46,36 @@ __global__ __launch_bounds__(256) void guide_mean_partial_kernel(
     for (int k = 0; k < kMaxD; ++k)
       if (k < t.n) acc[k] += monomial(t, k, iv);
   }
-  for (int k = 0; k < t.n; ++k) {
-    double v = 0.0;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < kMaxD; ++q)
-      if (q == k) v = acc[q];
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
+  for (int k = 0; k < kMaxD; ++k) {
+    if (k < t.n) {
+      const double v = wave_sum(acc[k]);
+      if (lane == 0) red[wv][k] = v;
     }
-    if (threadIdx.x == 0) partial[blockIdx.x * kMaxD + k] = red[0];
-    __syncthreads();
   }
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k < t.n) partial[blockIdx.x * kMaxD + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
 }
 
+// One block per channel: the kMeanBlocks partial sums in a fixed order.
 __global__ __launch_bounds__(256) void guide_mean_final_kernel(
-    const double* __restrict__ partial, int nblocks, int n, int P, int centre,
+    const double* __restrict__ partial, int nblocks, int P, int centre,
     double* __restrict__ shift) {
-  // one thread per partial block, fixed-order tree per channel (deterministic)
-  __shared__ double red[256];
-  for (int k = 0; k < n; ++k) {
-    red[threadIdx.x] = threadIdx.x < nblocks ? partial[threadIdx.x * kMaxD + k] : 0.0;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) shift[k] = centre ? red[0] / static_cast<double>(P) : 0.0;
-    __syncthreads();
+  __shared__ double red[4];
+  const int k = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) v += partial[b * kMaxD + k];
+  v = wave_sum(v);
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double tot = ((red[0] + red[1]) + red[2]) + red[3];
+    shift[k] = centre ? tot / static_cast<double>(P) : 0.0;
   }
 }
 
@@ -78,21 +85,17 @@ __global__ __launch_bounds__(256) void guide_mean_final_kernel(
 __global__ __launch_bounds__(256) void guide_synth_kernel(
     const float* __restrict__ I, int P, MonoTable t, const double* __restrict__ shift,
     float* __restrict__ g32, double* __restrict__ g64) {
-  const int n1 = t.n + 1;
-  const size_t idx = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
-  const size_t total = static_cast<size_t>(P) * n1;
-  if (idx >= total) return;
-  const int k = static_cast<int>(idx / P);
-  const int p = static_cast<int>(idx - static_cast<size_t>(k) * P);
-  if (k == 0) {
-    g32[idx] = 1.0f;
-    return;
-  }
+  const int p = static_cast<int>(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= P) return;
   float iv[4] = {0.f, 0.f, 0.f, 0.f};
   for (int c = 0; c < t.m; ++c) iv[c] = I[static_cast<size_t>(c) * P + p];
-  const double g = monomial(t, k - 1, iv) - shift[k - 1];
-  g64[static_cast<size_t>(p) * t.n + (k - 1)] = g;
-  g32[idx] = static_cast<float>(g);
+  g32[p] = 1.0f;
+  double* __restrict__ row = g64 + static_cast<size_t>(p) * t.n;
+  for (int k = 0; k < t.n; ++k) {
+    const double g = monomial(t, k, iv) - shift[k];
+    row[k] = g;
+    g32[static_cast<size_t>(k + 1) * P + p] = static_cast<float>(g);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -269,6 +272,102 @@ __global__ __launch_bounds__(64) void invert_kernel(
   for (int q = 0; q < PD; ++q) minv_out[static_cast<size_t>(p) * PD + q] = static_cast<MT>(M[q]);
 }
 
+// Large systems (D >= 11): the same recursion with the rows of M spread over
+// kLpp lanes per pixel (lane q owns rows q, q + kLpp, ...), so the matrix
+// stays in registers.  Each step forms u for the owned rows, gathers all of u
+// within the lane group with shuffles, and every lane of the group computes
+// the same Schur complement.  The rank-one update uses the symmetric product
+// u_i u_j, so the stored M stays exactly symmetric.
+constexpr int kLpp = 8;
+
+template <int D, int RIDGE>
+__global__ __launch_bounds__(256) void invert_lanes_kernel(
+    const double* __restrict__ S, int H, int W, int R, double eps,
+    double* __restrict__ mu_out, void* __restrict__ minv_void) {
+  using MT = typename std::conditional<RIDGE != 0, double, float>::type;
+  MT* __restrict__ minv_out = static_cast<MT*>(minv_void);
+  constexpr int NG = RIDGE ? D - 1 : D;
+  constexpr int K = NG + NG * (NG + 1) / 2;
+  constexpr int PD = D * (D + 1) / 2;
+  constexpr int NR = (D + kLpp - 1) / kLpp;  // rows per lane
+  const int q = threadIdx.x % kLpp;
+  const int pr = static_cast<int>(blockIdx.x) * (256 / kLpp) + static_cast<int>(threadIdx.x) / kLpp;
+  // lanes of a pixel past the image idle through the arithmetic on pixel 0
+  // and store nothing (the shuffles need every lane of the group)
+  const bool live = pr < H * W;
+  const int p = live ? pr : 0;
+  const int y = p / W;
+  const int x = p - y * W;
+  const double Np = static_cast<double>(window_count(x, y, W, H, R));
+  const double* s = S + static_cast<size_t>(p) * K;
+
+  auto A = [&](int i, int j) -> double {
+    if (!RIDGE) {
+      const double mi = s[i] / Np, mj = s[j] / Np;
+      return s[NG + packed_index(i, j, NG)] / Np - mi * mj + (i == j ? eps : 0.0);
+    }
+    if (i == 0) return (j == 0) ? Np + eps : s[j - 1];
+    return s[NG + packed_index(i - 1, j - 1, NG)] + (i == j ? eps : 0.0);
+  };
+
+  double M[NR][D];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int j = 0; j < D; ++j) M[r][j] = 0.0;
+  if (q == 0) M[0][0] = 1.0 / A(0, 0);
+#pragma unroll
+  for (int kap = 1; kap < D; ++kap) {
+    double g[D];
+#pragma unroll
+    for (int j = 0; j < kap; ++j) g[j] = A(j, kap);
+    double u[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < kap; ++j) acc = fma(M[r][j], g[j], acc);
+      u[r] = (q + kLpp * r < kap) ? acc : 0.0;
+    }
+    double uj[D];
+#pragma unroll
+    for (int j = 0; j < kap; ++j) uj[j] = __shfl(u[j / kLpp], j % kLpp, kLpp);
+    double schur = A(kap, kap);
+#pragma unroll
+    for (int j = 0; j < kap; ++j) schur = fma(-g[j], uj[j], schur);
+    const double inv = 1.0 / schur;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (q + kLpp * r < kap) {
+#pragma unroll
+        for (int j = 0; j < kap; ++j) M[r][j] = fma(u[r] * uj[j], inv, M[r][j]);
+        M[r][kap] = -u[r] * inv;
+      }
+    }
+    if (q == kap % kLpp) {
+#pragma unroll
+      for (int j = 0; j < kap; ++j) M[kap / kLpp][j] = -uj[j] * inv;
+      M[kap / kLpp][kap] = inv;
+    }
+  }
+  if (!live) return;
+  if (!RIDGE && q == 0) {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) mu_out[static_cast<size_t>(p) * NG + i] = s[i] / Np;
+  }
+  MT* __restrict__ o = minv_out + static_cast<size_t>(p) * PD;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = q + kLpp * r;
+    if (i < D) {
+      const int base = packed_index(i, i, D) - i;  // index of (i, j) is base + j
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if (j >= i) o[base + j] = static_cast<MT>(M[r][j]);
+    }
+  }
+}
+
 // Same recursion over a batch of dense SPD matrices (upper triangle read).
 template <int D>
 __global__ __launch_bounds__(64) void spd_inverse_kernel(const double* __restrict__ a,
@@ -321,25 +420,25 @@ hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t,
   const int P = H * W;
   hipLaunchKernelGGL(guide_mean_partial_kernel, dim3(kMeanBlocks), dim3(256), 0, s, I, P, t,
                      partial);
-  hipLaunchKernelGGL(guide_mean_final_kernel, dim3(1), dim3(256), 0, s, partial, kMeanBlocks,
-                     t.n, P, centre ? 1 : 0, shift);
+  hipLaunchKernelGGL(guide_mean_final_kernel, dim3(t.n), dim3(256), 0, s, partial, kMeanBlocks,
+                     P, centre ? 1 : 0, shift);
   return hipGetLastError();
 }
 
 hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
                               const double* shift, float* g32, double* g64, hipStream_t s) {
   const int P = H * W;
-  const size_t total = static_cast<size_t>(P) * (t.n + 1);
-  const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+  const unsigned blocks = static_cast<unsigned>((P + 255) / 256);
   hipLaunchKernelGGL(guide_synth_kernel, dim3(blocks), dim3(256), 0, s, I, P, t, shift, g32,
                      g64);
   return hipGetLastError();
 }
 
 template <int R>
-static hipError_t moments_r(const double* g64, int n, int H, int W, double* S, hipStream_t s) {
+static hipError_t moments_r(const double* g64, int n, int H, int W, int target, double* S,
+                           hipStream_t s) {
   const int K = n + n * (n + 1) / 2;
-  StripGrid g = strip_grid(H, W, R, (K + 255) / 256, 2048);
+  StripGrid g = strip_grid(H, W, R, (K + 255) / 256, target);
   dim3 grid(static_cast<unsigned>(g.strips * g.bands), static_cast<unsigned>((K + 255) / 256));
   const int threads = K >= 256 ? 256 : ((K + 63) / 64) * 64;
   hipLaunchKernelGGL(moments_kernel<R>, grid, dim3(threads), 0, s, g64, n, K, H, W, g.band_h,
@@ -347,12 +446,12 @@ static hipError_t moments_r(const double* g64, int n, int H, int W, double* S, h
   return hipGetLastError();
 }
 
-hipError_t launch_moments(const double* g64, int n, int H, int W, int R, double* S,
-                          hipStream_t s) {
+hipError_t launch_moments(const double* g64, int n, int H, int W, int R, int target,
+                          double* S, hipStream_t s) {
   switch (R) {
 #define HGF_MOMENTS_CASE(r) \
   case r:                   \
-    return moments_r<r>(g64, n, H, W, S, s);
+    return moments_r<r>(g64, n, H, W, target, S, s);
     HGF_MOMENTS_CASE(1)
     HGF_MOMENTS_CASE(2)
     HGF_MOMENTS_CASE(4)
@@ -368,8 +467,14 @@ template <int D, int RIDGE>
 static hipError_t invert_d(const double* S, int H, int W, int R, double eps, double* mu,
                            void* minv, hipStream_t s) {
   const int P = H * W;
-  hipLaunchKernelGGL((invert_kernel<D, RIDGE>), dim3((P + 63) / 64), dim3(64), 0, s, S, H, W, R,
-                     eps, mu, minv);
+  if constexpr (D >= 11) {
+    constexpr int per_block = 256 / kLpp;
+    hipLaunchKernelGGL((invert_lanes_kernel<D, RIDGE>), dim3((P + per_block - 1) / per_block),
+                       dim3(256), 0, s, S, H, W, R, eps, mu, minv);
+  } else {
+    hipLaunchKernelGGL((invert_kernel<D, RIDGE>), dim3((P + 63) / 64), dim3(64), 0, s, S, H, W,
+                       R, eps, mu, minv);
+  }
   return hipGetLastError();
 }
 

@@ -50,31 +50,22 @@ bool config_supported(int n, int R, int reg) {
   return n_ok && radius_supported(R);
 }
 
-// Tuning overrides for the strip decomposition (HGF_TARGET_BLOCKS,
-// HGF_MIN_BAND, HGF_MAX_BAND), read once; used by measurement sweeps.
-static int env_int(const char* name, int dflt) {
-  const char* v = std::getenv(name);
-  if (v == nullptr || *v == 0) return dflt;
-  const int x = std::atoi(v);
-  return x > 0 ? x : dflt;
-}
-
-// Strips of (sin - 2R) output columns, label chunks, and bands whose height
-// is chosen so that the grid has about target_blocks blocks.  Each band
+// Strips of (sin - 2R) output columns, label chunks, and as many bands as fit
+// in target_blocks (never more: a grid slightly larger than a multiple of the
+// resident workgroup slots leaves a nearly empty last round).  Each band
 // restarts the vertical running sums (2R + 1 rows of set-up), so bands are at
 // least kMinBand rows; at most kMaxBand rows bound the float32 drift of the
 // running sums.
+constexpr int kMinBand = 4;
+constexpr int kMaxBand = 64;
+
 StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_blocks) {
-  static const int kTarget = env_int("HGF_TARGET_BLOCKS", 0);
-  static const int kMinBand = env_int("HGF_MIN_BAND", 4);
-  static const int kMaxBand = env_int("HGF_MAX_BAND", 64);
-  if (kTarget > 0) target_blocks = kTarget;
   StripGrid g;
   const int sout = sin - 2 * R;
   g.strips = (W + sout - 1) / sout;
   g.chunks = chunks;
   const int per_band = std::max(1, g.strips * chunks);
-  const int bands = std::max(1, (target_blocks + per_band - 1) / per_band);
+  const int bands = std::max(1, target_blocks / per_band);
   int band_h = (H + bands - 1) / bands;
   band_h = std::min(kMaxBand, std::max(kMinBand, band_h));
   g.band_h = band_h;
@@ -370,7 +361,7 @@ hgf_status run_guide(hgf_context* ctx, const Plan& pl, const float* guide, void*
   {
     Stage st(ctx, 2, s);
     HGF_TRY(launch_moments(at<double>(ws, pl.off_g64), pl.n, pl.H, pl.W, pl.R,
-                           at<double>(ws, pl.off_x), s),
+                           tuned_target(ctx, kTuneMoments, pl), at<double>(ws, pl.off_x), s),
             "moments");
   }
   {
@@ -423,7 +414,7 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
     oa.W = pl.W;
     oa.R = pl.R;
     oa.label_count = lc;
-    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, out_strip_width(pl.n + 1 > 10 ? 2 : 1), chunks,
+    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, out_strip_width(pl.n), chunks,
                            out_target);
     {
       Stage st(ctx, 5, s);

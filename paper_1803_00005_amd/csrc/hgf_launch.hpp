@@ -27,8 +27,10 @@ StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_bloc
 // per wave and 64 columns; above, two channels per wave and a narrower strip
 // so that ten waves fit the register file.
 constexpr int coef_strip_width(int n) { return n + 1 > 10 ? 38 : 64; }
-// State columns per strip of the output kernel for 1 or 2 channels per wave.
-constexpr int out_strip_width(int cpw) { return cpw > 1 ? 32 : 64; }
+// Output kernel: channels per wave (ten waves at most) and state columns per
+// strip for n guidance channels (two channels per wave leave room for 48).
+constexpr int out_channels_per_wave(int n) { return n + 1 > 10 ? 2 : 1; }
+constexpr int out_strip_width(int n) { return out_channels_per_wave(n) > 1 ? 48 : 64; }
 
 // Radii with compiled strip kernels.
 bool radius_supported(int R);
@@ -49,7 +51,7 @@ hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
                               hipStream_t s);
 // a2: window sums of G_i and G_i G_j (i <= j), float64 [P][K], K = n + n(n+1)/2.
 hipError_t launch_moments(const double* g64, int n, int H, int W, int R,
-                          double* S, hipStream_t s);
+                          int target_blocks, double* S, hipStream_t s);
 // a3: per-pixel window mean mu [P][n] (covariance form) and the packed inverse
 // [P][D(D+1)/2] by the bordering recursion of Prop. 1, computed in float64 and
 // stored as float32 (covariance form) or float64 (ridge form).
@@ -98,6 +100,16 @@ struct OutLaunch {
 };
 // a6 + a7: coefficient box filter, output and winner-takes-all keys.
 hipError_t launch_out(const OutLaunch& a, hipStream_t s);
+hipError_t launch_out_n1(const OutLaunch& a, hipStream_t s);
+hipError_t launch_out_n2(const OutLaunch& a, hipStream_t s);
+hipError_t launch_out_n3(const OutLaunch& a, hipStream_t s);
+hipError_t launch_out_n4(const OutLaunch& a, hipStream_t s);
+hipError_t launch_out_n5(const OutLaunch& a, hipStream_t s);
+hipError_t launch_out_n6(const OutLaunch& a, hipStream_t s);
+hipError_t launch_out_n7(const OutLaunch& a, hipStream_t s);
+hipError_t launch_out_n8(const OutLaunch& a, hipStream_t s);
+hipError_t launch_out_n9(const OutLaunch& a, hipStream_t s);
+hipError_t launch_out_n19(const OutLaunch& a, hipStream_t s);
 
 // Fill `count` keys with ~0 (no hipMemsetAsync: safe under graph capture).
 hipError_t launch_key_fill(unsigned long long* keys, size_t count, hipStream_t s);

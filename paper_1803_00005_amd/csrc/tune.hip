@@ -19,11 +19,12 @@ using namespace hgf;
 
 namespace {
 
-// Milliseconds of the coefficient (stage 4) and output (stage 5) kernels of
-// `reps` label passes with the current table.
-hgf_status time_labels(hgf_context* ctx, const Plan& pl, const void* cost, int cost_ld,
-                       float* out, int out_ld, void* ws, int reps, hipStream_t s, double* coef_ms,
-                       double* out_ms) {
+// Milliseconds per pass of the guidance moment sums (stage 2), the
+// coefficient (stage 4) and the output (stage 5) kernels over `reps` passes
+// of the whole path with the current table.
+hgf_status time_path(hgf_context* ctx, const Plan& pl, const float* guide, const void* cost,
+                     int cost_ld, float* out, int out_ld, void* ws, int reps, hipStream_t s,
+                     double* ms_out) {
   const bool timing = ctx->timing;
   ctx->timing = true;
   double ms[HGF_NUM_STAGES];
@@ -31,6 +32,8 @@ hgf_status time_labels(hgf_context* ctx, const Plan& pl, const void* cost, int c
   hgf_status st = HGF_OK;
   unsigned long long* keys = at<unsigned long long>(ws, pl.off_keys);
   for (int r = 0; r < reps && st == HGF_OK; ++r) {
+    st = run_guide(ctx, pl, guide, ws, s);
+    if (st != HGF_OK) break;
     if (launch_key_fill(keys, pl.P, s) != hipSuccess) {
       st = fail(HGF_E_DEVICE, "key_fill");
       break;
@@ -43,8 +46,7 @@ hgf_status time_labels(hgf_context* ctx, const Plan& pl, const void* cost, int c
   ctx->timing = timing;
   if (st != HGF_OK) return st;
   if (st2 != HGF_OK) return st2;
-  *coef_ms = ms[4] / reps;
-  *out_ms = ms[5] / reps;
+  for (int k = 0; k < HGF_NUM_STAGES; ++k) ms_out[k] = ms[k] / reps;
   return HGF_OK;
 }
 
@@ -71,35 +73,34 @@ hgf_status hgf_autotune(hgf_context* ctx, const hgf_params* params, const float*
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int cost_ld = params->cost_ld ? params->cost_ld : params->num_labels;
   const int out_ld = params->out_ld ? params->out_ld : params->num_labels;
-  st = run_guide(ctx, pl, guide, ws, s);
-  if (st != HGF_OK) return st;
+  double ms[HGF_NUM_STAGES];
   // one untimed pass to warm caches and code objects
-  double c0 = 0, o0 = 0;
-  st = time_labels(ctx, pl, cost, cost_ld, out, out_ld, ws, 1, s, &c0, &o0);
+  st = time_path(ctx, pl, guide, cost, cost_ld, out, out_ld, ws, 1, s, ms);
   if (st != HGF_OK) return st;
-  const TuneKey kc = tune_key(kTuneCoef, pl);
-  const TuneKey ko = tune_key(kTuneOut, pl);
-  double best_c = std::numeric_limits<double>::max(), best_o = best_c;
-  int arg_c = kDefaultTarget, arg_o = kDefaultTarget;
+  const int kernels[3] = {kTuneMoments, kTuneCoef, kTuneOut};
+  const int stage_of[3] = {2, 4, 5};
+  TuneKey keys[3];
+  double best[3];
+  int arg[3];
+  for (int k = 0; k < 3; ++k) {
+    keys[k] = tune_key(kernels[k], pl);
+    best[k] = std::numeric_limits<double>::max();
+    arg[k] = kDefaultTarget;
+  }
   for (int cand : tune_candidates()) {
-    ctx->tune[kc] = cand;
-    ctx->tune[ko] = cand;
-    double cm = 0, om = 0;
-    st = time_labels(ctx, pl, cost, cost_ld, out, out_ld, ws, 3, s, &cm, &om);
+    for (int k = 0; k < 3; ++k) ctx->tune[keys[k]] = cand;
+    st = time_path(ctx, pl, guide, cost, cost_ld, out, out_ld, ws, 3, s, ms);
     if (st != HGF_OK) return st;
-    if (cm < best_c) {
-      best_c = cm;
-      arg_c = cand;
-    }
-    if (om < best_o) {
-      best_o = om;
-      arg_o = cand;
+    for (int k = 0; k < 3; ++k) {
+      if (ms[stage_of[k]] < best[k]) {
+        best[k] = ms[stage_of[k]];
+        arg[k] = cand;
+      }
     }
   }
-  ctx->tune[kc] = arg_c;
-  ctx->tune[ko] = arg_o;
+  for (int k = 0; k < 3; ++k) ctx->tune[keys[k]] = arg[k];
   // leave `out` holding what hgf_filter now computes with the chosen table
-  if (out != nullptr) st = time_labels(ctx, pl, cost, cost_ld, out, out_ld, ws, 1, s, &c0, &o0);
+  if (out != nullptr) st = time_path(ctx, pl, guide, cost, cost_ld, out, out_ld, ws, 1, s, ms);
   return st;
 }
 

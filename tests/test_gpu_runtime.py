@@ -169,8 +169,8 @@ def test_autotune_and_table_io(data, tmp_path):
     out = torch.empty(w.height, w.width, w.labels, dtype=torch.float32, device=dev())
     ctx.autotune(g, c, radius=w.radius, eps=w.eps, degree=w.degree, out=out)
     rows = ctx.tune_entries()
-    assert len(rows) == 2
-    assert {r[0] for r in rows} == {0, 1}
+    assert len(rows) == 3
+    assert {r[0] for r in rows} == {0, 1, 2}
     for r in rows:
         assert r[1] == w.n and r[2] == w.radius and r[6] >= 1
     # the tuned path still meets the bar
