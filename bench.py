@@ -199,7 +199,7 @@ def sampled_error(w: synth.Workload, guide, cost, Z, lab, k: int = 14, seed: int
 # plain form: one image per call
 # ----------------------------------------------------------------------------
 
-def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True):
+def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True, autotune=True):
     import torch
 
     from paper_1803_00005_amd import hgf
@@ -215,6 +215,14 @@ def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True):
         ctx.filter(g_d, c_d, radius=w.radius, eps=w.eps, degree=w.degree, basis=w.basis,
                    out=Z, labels=lab, workspace=ws, stream=stream)
 
+    if autotune:
+        # untimed set-up: the strip decomposition for this size class is chosen
+        # by timing the candidates on these inputs (hgf_autotune)
+        ctx.autotune(g_d, c_d, radius=w.radius, eps=w.eps, degree=w.degree, basis=w.basis,
+                     stream=stream)
+    tuned = [r for r in ctx.tune_entries() if r[1] == w.n and r[2] == w.radius
+             and r[4] == (1 if w.cost_dtype == "bf16" else 0)
+             and r[5] == (w.pixels.bit_length() - 1)]
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -253,10 +261,11 @@ def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True):
         mdl = {k: v / (cnt / steps) for k, v in model[dom["stage"]].items()}
         roof = roofline_of(KERNEL_NAMES.get(dom["stage"], dom["stage"]), mdl,
                            dom["ms_per_launch"], measured_traffic(w.name, dom["stage"]))
-    return {"ms": ms, "stages": rows, "roofline": roof, "Z": Z, "labels": lab}
+    return {"ms": ms, "stages": rows, "roofline": roof, "Z": Z, "labels": lab,
+            "tuning": {["coef", "out", "moments"][r[0]]: r[6] for r in tuned}}
 
 
-def secondary_n19(ctx, steps, warmup, check):
+def secondary_n19(ctx, steps, warmup, check, autotune=True):
     import torch
     out = []
     for name in ("voronoi1242x375_n19_L128", "voronoi1242x375_n19_L128_bf16"):
@@ -267,8 +276,9 @@ def secondary_n19(ctx, steps, warmup, check):
         c_d = torch.from_numpy(cost).cuda()
         if w.cost_dtype == "bf16":
             c_d = c_d.to(torch.bfloat16)
-        r = run_plain(ctx, w, g_d, c_d, steps, warmup)
+        r = run_plain(ctx, w, g_d, c_d, steps, warmup, autotune=autotune)
         rec = {"form": "plain", "workload": w.name, "value": w.pixel_labels / r["ms"] / 1e3,
+               "tuning": {"target_blocks": r["tuning"]},
                "unit": UNIT, "ms_per_step": r["ms"], "n": w.n, "labels": w.labels,
                "cost_dtype": w.cost_dtype, "roofline": r["roofline"], "stages": r["stages"]}
         if check:
@@ -463,6 +473,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-stage-timing", action="store_true")
+    ap.add_argument("--tune-file", default=None,
+                    help="tuning table to load (default: the one shipped with the package, "
+                         "if present); 'none' keeps the built-in defaults")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the strip decomposition on each plain workload before timing it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device fill and sums (reference for the HBM "
                          "byte counters)")
@@ -498,6 +513,14 @@ def main():
     if w.cost_dtype == "bf16":
         c_d = c_d.to(torch.bfloat16)
     ctx = hgf.Context(0)
+    from paper_1803_00005_amd import tune_table
+    tune_file = args.tune_file if args.tune_file is not None else (
+        tune_table.DEFAULT_TABLE if os.path.exists(tune_table.DEFAULT_TABLE) else "none")
+    if tune_file != "none":
+        ctx.tune_load(tune_file)
+        say(f"tuning table {tune_file}: {len(ctx.tune_entries())} entries")
+    tuning_source = "autotune" if args.autotune else (
+        os.path.relpath(tune_file, ROOT) if tune_file != "none" else "built-in defaults")
 
     if args.copy_calibration:
         # a fill (writes 1 GiB) and a sum (reads 1 GiB): known byte counts for
@@ -510,7 +533,8 @@ def main():
         del src
 
     t0 = time.perf_counter()
-    r = run_plain(ctx, w, g_d, c_d, args.steps, args.warmup, not args.no_stage_timing)
+    r = run_plain(ctx, w, g_d, c_d, args.steps, args.warmup, not args.no_stage_timing,
+                  autotune=args.autotune)
     ms = r["ms"]
     say(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {time.perf_counter() - t0:.3f} s)")
     value = w.pixel_labels / (ms * 1e-3) / 1e6
@@ -518,7 +542,8 @@ def main():
 
     sec = []
     if "n19" in secondary:
-        sec += secondary_n19(ctx, max(3, args.steps // 2), args.warmup, not args.no_check)
+        sec += secondary_n19(ctx, max(3, args.steps // 2), args.warmup, not args.no_check,
+                             autotune=args.autotune)
     if "batch" in secondary:
         sec.append(secondary_batch(ctx, args.batch_count, args.batch_steps, 1,
                                    not args.no_check))
@@ -535,6 +560,7 @@ def main():
                    "eps": w.eps, "cost_dtype": w.cost_dtype, "reg": "covariance",
                    "pixel_labels_per_step": w.pixel_labels},
         "roofline": r["roofline"], "cpu_baseline": cpu, "error": err, "stages": r["stages"],
+        "tuning": {"source": tuning_source, "target_blocks": r["tuning"]},
         "secondary": sec, "source_hash": source_hash(),
     }
     print(json.dumps(line), flush=True)

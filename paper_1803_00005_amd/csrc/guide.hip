@@ -220,16 +220,17 @@ __global__ __launch_bounds__(64) void invert_kernel(
   const int y = p / W;
   const int x = p - y * W;
   const double Np = static_cast<double>(window_count(x, y, W, H, R));
+  const double invN = 1.0 / Np;
   const double* s = S + static_cast<size_t>(p) * K;
 
   double mu[NG];
 #pragma unroll
-  for (int i = 0; i < NG; ++i) mu[i] = RIDGE ? 0.0 : s[i] / Np;
+  for (int i = 0; i < NG; ++i) mu[i] = RIDGE ? 0.0 : s[i] * invN;
 
   // entry (i, j), i <= j, of the regularised system
   auto A = [&](int i, int j) -> double {
     if (!RIDGE) {
-      return s[NG + packed_index(i, j, NG)] / Np - mu[i] * mu[j] + (i == j ? eps : 0.0);
+      return fma(s[NG + packed_index(i, j, NG)], invN, -mu[i] * mu[j]) + (i == j ? eps : 0.0);
     }
     if (i == 0) return (j == 0) ? Np + eps : s[j - 1];
     return s[NG + packed_index(i - 1, j - 1, NG)] + (i == j ? eps : 0.0);
@@ -273,15 +274,41 @@ __global__ __launch_bounds__(64) void invert_kernel(
 }
 
 // Large systems (D >= 11): the same recursion with the rows of M spread over
-// kLpp lanes per pixel (lane q owns rows q, q + kLpp, ...), so the matrix
-// stays in registers.  Each step forms u for the owned rows, gathers all of u
-// within the lane group with shuffles, and every lane of the group computes
-// the same Schur complement.  The rank-one update uses the symmetric product
-// u_i u_j, so the stored M stays exactly symmetric.
-constexpr int kLpp = 8;
+// the kLpp = 4 lanes of a quad (lane q owns rows q, q + 4, ...), so the matrix
+// stays in registers.  Values move within the quad by DPP broadcasts (plain
+// vector ALU operations, no LDS round trip).  Every lane of the quad computes
+// the same Schur complement, reduced in a fixed order.  The rank-one update
+// uses the symmetric product u_i u_j, so the stored M stays exactly symmetric.
+constexpr int kLpp = 4;
+// threads per block of the lane inverse: two blocks fit a CU, so one stages
+// its window sums while the other computes
+constexpr int kInvBlock = 128;
+
+// Value of lane K of this lane's quad.
+template <int K>
+__device__ __forceinline__ double quad_bcast(double v) {
+  constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the quad, the same association in every lane.
+__device__ __forceinline__ double quad_sum(double v) {
+  constexpr int swap1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);
+  constexpr int swap2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+  auto perm = [](double x, auto ctrl_tag) {
+    constexpr int c = decltype(ctrl_tag)::value;
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), c, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), c, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+  };
+  v = v + perm(v, std::integral_constant<int, swap1>());
+  return v + perm(v, std::integral_constant<int, swap2>());
+}
 
 template <int D, int RIDGE>
-__global__ __launch_bounds__(256) void invert_lanes_kernel(
+__global__ __launch_bounds__(kInvBlock) void invert_lanes_kernel(
     const double* __restrict__ S, int H, int W, int R, double eps,
     double* __restrict__ mu_out, void* __restrict__ minv_void) {
   using MT = typename std::conditional<RIDGE != 0, double, float>::type;
@@ -291,20 +318,41 @@ __global__ __launch_bounds__(256) void invert_lanes_kernel(
   constexpr int PD = D * (D + 1) / 2;
   constexpr int NR = (D + kLpp - 1) / kLpp;  // rows per lane
   const int q = threadIdx.x % kLpp;
-  const int pr = static_cast<int>(blockIdx.x) * (256 / kLpp) + static_cast<int>(threadIdx.x) / kLpp;
+  const int pr = static_cast<int>(blockIdx.x) * (kInvBlock / kLpp) + static_cast<int>(threadIdx.x) / kLpp;
   // lanes of a pixel past the image idle through the arithmetic on pixel 0
-  // and store nothing (the shuffles need every lane of the group)
+  // and store nothing (the broadcasts need every lane of the quad)
   const bool live = pr < H * W;
   const int p = live ? pr : 0;
   const int y = p / W;
   const int x = p - y * W;
   const double Np = static_cast<double>(window_count(x, y, W, H, R));
-  const double* s = S + static_cast<size_t>(p) * K;
+  const double invN = 1.0 / Np;
 
+  // The block's window sums (64 pixels x K, contiguous) are copied to LDS
+  // first with coalesced direct-to-LDS loads; the recursion then reads them
+  // at LDS latency.
+  __shared__ double Ss[(kInvBlock / kLpp) * K];
+  {
+    const int p0 = static_cast<int>(blockIdx.x) * (kInvBlock / kLpp);
+    const int cnt = min(kInvBlock / kLpp, H * W - p0);
+    const int dwords = cnt * K * 2;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(S + static_cast<size_t>(p0) * K);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(Ss);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int base = wv * 64; base < dwords; base += kInvBlock) {
+      const int i = min(base + lane, dwords - 1);
+      __builtin_amdgcn_global_load_lds(src + i, dst + base, 4, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  const double* s = Ss + (static_cast<int>(threadIdx.x) / kLpp) * K;
+
+  // one reciprocal per pixel; every entry is then formed with products only
   auto A = [&](int i, int j) -> double {
     if (!RIDGE) {
-      const double mi = s[i] / Np, mj = s[j] / Np;
-      return s[NG + packed_index(i, j, NG)] / Np - mi * mj + (i == j ? eps : 0.0);
+      const double mi = s[i] * invN, mj = s[j] * invN;
+      return fma(s[NG + packed_index(i, j, NG)], invN, -mi * mj) + (i == j ? eps : 0.0);
     }
     if (i == 0) return (j == 0) ? Np + eps : s[j - 1];
     return s[NG + packed_index(i - 1, j - 1, NG)] + (i == j ? eps : 0.0);
@@ -316,44 +364,59 @@ __global__ __launch_bounds__(256) void invert_lanes_kernel(
 #pragma unroll
     for (int j = 0; j < D; ++j) M[r][j] = 0.0;
   if (q == 0) M[0][0] = 1.0 / A(0, 0);
+  // value of quad lane k (k is a constant once the loops below are unrolled)
+  auto bcast = [](double v, int k) -> double {
+    switch (k) {
+      case 0: return quad_bcast<0>(v);
+      case 1: return quad_bcast<1>(v);
+      case 2: return quad_bcast<2>(v);
+      default: return quad_bcast<3>(v);
+    }
+  };
 #pragma unroll
   for (int kap = 1; kap < D; ++kap) {
-    double g[D];
+    // column kap of the system: lane q forms the entries j = q mod 4
+    double gq[NR];
 #pragma unroll
-    for (int j = 0; j < kap; ++j) g[j] = A(j, kap);
+    for (int r = 0; r < NR; ++r) {
+      const int j = q + kLpp * r;
+      gq[r] = (j < kap) ? A(j, kap) : 0.0;
+    }
+    // u = M g for the owned rows
     double u[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      double acc = 0.0;
+    for (int r = 0; r < NR; ++r) u[r] = 0.0;
 #pragma unroll
-      for (int j = 0; j < kap; ++j) acc = fma(M[r][j], g[j], acc);
-      u[r] = (q + kLpp * r < kap) ? acc : 0.0;
+    for (int j = 0; j < kap; ++j) {
+      const double gj = bcast(gq[j / kLpp], j % kLpp);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) u[r] = fma(M[r][j], gj, u[r]);
     }
-    double uj[D];
-#pragma unroll
-    for (int j = 0; j < kap; ++j) uj[j] = __shfl(u[j / kLpp], j % kLpp, kLpp);
-    double schur = A(kap, kap);
-#pragma unroll
-    for (int j = 0; j < kap; ++j) schur = fma(-g[j], uj[j], schur);
-    const double inv = 1.0 / schur;
+    double part = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      if (q + kLpp * r < kap) {
-#pragma unroll
-        for (int j = 0; j < kap; ++j) M[r][j] = fma(u[r] * uj[j], inv, M[r][j]);
-        M[r][kap] = -u[r] * inv;
-      }
+      if (q + kLpp * r >= kap) u[r] = 0.0;
+      part = fma(gq[r], u[r], part);
     }
-    if (q == kap % kLpp) {
+    const double inv = 1.0 / (A(kap, kap) - quad_sum(part));
+    // M <- [[M + u u^T / s, -u / s], [-u^T / s, 1 / s]]
 #pragma unroll
-      for (int j = 0; j < kap; ++j) M[kap / kLpp][j] = -uj[j] * inv;
-      M[kap / kLpp][kap] = inv;
+    for (int j = 0; j < kap; ++j) {
+      const double uj = bcast(u[j / kLpp], j % kLpp);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (q + kLpp * r < kap) M[r][j] = fma(u[r] * uj, inv, M[r][j]);
+      if (q == kap % kLpp) M[kap / kLpp][j] = -uj * inv;
     }
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (q + kLpp * r < kap) M[r][kap] = -u[r] * inv;
+    if (q == kap % kLpp) M[kap / kLpp][kap] = inv;
   }
   if (!live) return;
   if (!RIDGE && q == 0) {
 #pragma unroll
-    for (int i = 0; i < NG; ++i) mu_out[static_cast<size_t>(p) * NG + i] = s[i] / Np;
+    for (int i = 0; i < NG; ++i) mu_out[static_cast<size_t>(p) * NG + i] = s[i] * invN;
   }
   MT* __restrict__ o = minv_out + static_cast<size_t>(p) * PD;
 #pragma unroll
@@ -468,9 +531,9 @@ static hipError_t invert_d(const double* S, int H, int W, int R, double eps, dou
                            void* minv, hipStream_t s) {
   const int P = H * W;
   if constexpr (D >= 11) {
-    constexpr int per_block = 256 / kLpp;
+    constexpr int per_block = kInvBlock / kLpp;
     hipLaunchKernelGGL((invert_lanes_kernel<D, RIDGE>), dim3((P + per_block - 1) / per_block),
-                       dim3(256), 0, s, S, H, W, R, eps, mu, minv);
+                       dim3(kInvBlock), 0, s, S, H, W, R, eps, mu, minv);
   } else {
     hipLaunchKernelGGL((invert_kernel<D, RIDGE>), dim3((P + 63) / 64), dim3(64), 0, s, S, H, W,
                        R, eps, mu, minv);
