@@ -449,6 +449,93 @@ def secondary_serve(ctx, requests, pool, rate, slots, arena_gb):
     return rec
 
 
+# ----------------------------------------------------------------------------
+# batched SPD inverse (Prop. 1) against the vendor solver's batched inverses
+# ----------------------------------------------------------------------------
+
+def secondary_inverse(count=1_000_000, sizes=(3, 5, 7, 9, 11, 13, 15, 17, 19), reps=5):
+    import torch
+
+    from paper_1803_00005_amd import hgf
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    rows = []
+    for D in sizes:
+        gen.manual_seed(100 + D)
+        X = torch.rand(count, D + 2, D, generator=gen, dtype=torch.float64, device=dev)
+        A = torch.bmm(X.transpose(1, 2).contiguous(), X)
+        A += 1e-3 * torch.eye(D, dtype=torch.float64, device=dev)
+        del X
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                out = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps, out
+
+        ms_h, Mh = timed(lambda: hgf.spd_inverse(A))
+        ms_lu, Ml = timed(lambda: torch.linalg.inv(A))
+        ms_ch, _ = timed(lambda: torch.cholesky_inverse(torch.linalg.cholesky(A)))
+        rel = float(((Mh - Ml).abs().amax(dim=(1, 2)) / Ml.abs().amax(dim=(1, 2))).max())
+        rows.append({"D": D, "ms_prop1": ms_h, "ms_lu": ms_lu, "ms_cholesky": ms_ch,
+                     "matrices_per_s": count / ms_h * 1e3, "speedup_vs_lu": ms_lu / ms_h,
+                     "speedup_vs_cholesky": ms_ch / ms_h, "max_rel_vs_lu": rel})
+        say(f"inverse D={D}: {ms_h:.3f} ms (LU {ms_lu:.3f}, Cholesky {ms_ch:.3f})")
+        del A, Mh, Ml
+        torch.cuda.empty_cache()
+    return {"form": "spd_inverse", "workload": f"spd{count}_D3-19", "matrices": count,
+            "reference": "torch.linalg.inv and torch.cholesky_inverse (vendor batched solver), "
+                         "float64", "rows": rows}
+
+
+# ----------------------------------------------------------------------------
+# gray guidance, power basis, one slice: the setting of the paper's timing tables
+# ----------------------------------------------------------------------------
+
+# the paper's own GPU times (Table 2, a GTX 960 with ArrayFire): context only
+PAPER_TABLE2_MS = {250: {3: 3.9, 5: 10.7, 7: 39.9, 9: 110.2},
+                   500: {3: 3.7, 5: 11.1, 7: 40.1, 9: 112.4},
+                   1000: {3: 4.1, 5: 10.9, 7: 41.3, 9: 115.9},
+                   2000: {3: 4.3, 5: 11.2, 7: 42.7, 9: 121.8}}
+
+
+def secondary_gray(ctx, sizes=(250, 500, 1000, 2000), ns=(3, 5, 7, 9), reps=10):
+    import torch
+    dev = torch.device("cuda", 0)
+    rows = []
+    for side in sizes:
+        for n in ns:
+            w = synth.Workload(name=f"gray{side}_n{n}", height=side, width=side, regions=40,
+                               labels=1, radius=7, eps=0.05, degree=n, disparity="planar",
+                               seed=9000 + side + n, guide_channels=1, basis="power")
+            g, c = synth.make_workload_device(w, dev)
+            f = lambda: ctx.filter(g, c, radius=w.radius, eps=w.eps, degree=w.degree,
+                                   basis="power", reg="ridge", want_labels=False)
+            f()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                f()
+            e1.record()
+            torch.cuda.synchronize()
+            rows.append({"side": side, "n": n, "ms": e0.elapsed_time(e1) / reps,
+                         "paper_gtx960_ms": PAPER_TABLE2_MS[side][n]})
+            del g, c
+    say("gray sweep: " + ", ".join(f"{r['side']}/{r['n']}: {r['ms']:.3f} ms" for r in rows[-4:]))
+    return {"form": "gray_power_ridge", "workload": "gray_power_r7_lambda0.05_L1",
+            "note": "one slice (L = 1) per filter, ridge form of Eq. 6 with the power basis; the "
+                    "paper's Table 2 times are from other hardware, for context",
+            "rows": rows}
+
+
 def say(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -461,8 +548,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(synth.WORKLOADS))
-    ap.add_argument("--secondary", default="n19,batch,serve",
-                    help="comma list of n19, batch, serve, or 'none'")
+    ap.add_argument("--secondary", default="n19,batch,serve,inverse,gray",
+                    help="comma list of n19, batch, serve, inverse, gray, or 'none'")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -489,7 +576,7 @@ def main():
         sys.exit(2)
     secondary = [] if args.secondary == "none" else [x for x in args.secondary.split(",") if x]
     for x in secondary:
-        if x not in ("n19", "batch", "serve"):
+        if x not in ("n19", "batch", "serve", "inverse", "gray"):
             ap.error(f"unknown secondary form {x!r}")
 
     w = synth.WORKLOADS[args.workload]
@@ -547,6 +634,10 @@ def main():
     if "batch" in secondary:
         sec.append(secondary_batch(ctx, args.batch_count, args.batch_steps, 1,
                                    not args.no_check))
+    if "inverse" in secondary:
+        sec.append(secondary_inverse())
+    if "gray" in secondary:
+        sec.append(secondary_gray(ctx))
     if "serve" in secondary:
         sec.append(secondary_serve(ctx, args.serve_requests, args.serve_pool, args.serve_rate,
                                    args.serve_slots, args.serve_arena_gb))

@@ -307,58 +307,14 @@ __device__ __forceinline__ double quad_sum(double v) {
   return v + perm(v, std::integral_constant<int, swap2>());
 }
 
-template <int D, int RIDGE>
-__global__ __launch_bounds__(kInvBlock) void invert_lanes_kernel(
-    const double* __restrict__ S, int H, int W, int R, double eps,
-    double* __restrict__ mu_out, void* __restrict__ minv_void) {
-  using MT = typename std::conditional<RIDGE != 0, double, float>::type;
-  MT* __restrict__ minv_out = static_cast<MT*>(minv_void);
-  constexpr int NG = RIDGE ? D - 1 : D;
-  constexpr int K = NG + NG * (NG + 1) / 2;
-  constexpr int PD = D * (D + 1) / 2;
-  constexpr int NR = (D + kLpp - 1) / kLpp;  // rows per lane
-  const int q = threadIdx.x % kLpp;
-  const int pr = static_cast<int>(blockIdx.x) * (kInvBlock / kLpp) + static_cast<int>(threadIdx.x) / kLpp;
-  // lanes of a pixel past the image idle through the arithmetic on pixel 0
-  // and store nothing (the broadcasts need every lane of the quad)
-  const bool live = pr < H * W;
-  const int p = live ? pr : 0;
-  const int y = p / W;
-  const int x = p - y * W;
-  const double Np = static_cast<double>(window_count(x, y, W, H, R));
-  const double invN = 1.0 / Np;
-
-  // The block's window sums (64 pixels x K, contiguous) are copied to LDS
-  // first with coalesced direct-to-LDS loads; the recursion then reads them
-  // at LDS latency.
-  __shared__ double Ss[(kInvBlock / kLpp) * K];
-  {
-    const int p0 = static_cast<int>(blockIdx.x) * (kInvBlock / kLpp);
-    const int cnt = min(kInvBlock / kLpp, H * W - p0);
-    const int dwords = cnt * K * 2;
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(S + static_cast<size_t>(p0) * K);
-    uint32_t* dst = reinterpret_cast<uint32_t*>(Ss);
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int base = wv * 64; base < dwords; base += kInvBlock) {
-      const int i = min(base + lane, dwords - 1);
-      __builtin_amdgcn_global_load_lds(src + i, dst + base, 4, 0, 0);
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-  }
-  const double* s = Ss + (static_cast<int>(threadIdx.x) / kLpp) * K;
-
-  // one reciprocal per pixel; every entry is then formed with products only
-  auto A = [&](int i, int j) -> double {
-    if (!RIDGE) {
-      const double mi = s[i] * invN, mj = s[j] * invN;
-      return fma(s[NG + packed_index(i, j, NG)], invN, -mi * mj) + (i == j ? eps : 0.0);
-    }
-    if (i == 0) return (j == 0) ? Np + eps : s[j - 1];
-    return s[NG + packed_index(i - 1, j - 1, NG)] + (i == j ? eps : 0.0);
-  };
-
-  double M[NR][D];
+// The bordered recursion of Prop. 1 (M = (lambda E + K)^-1 grown one row and
+// column at a time) over the quad: on return lane q holds rows q, q + 4, ...
+// of M in M[r][:].  A(i, j) returns entry (i, j), i <= j, of the system; each
+// lane calls it for its own rows and for the diagonal.
+template <int D, typename EntryFn>
+__device__ __forceinline__ void quad_bordered_inverse(EntryFn A, int q,
+                                                      double (&M)[(D + kLpp - 1) / kLpp][D]) {
+  constexpr int NR = (D + kLpp - 1) / kLpp;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -413,6 +369,61 @@ __global__ __launch_bounds__(kInvBlock) void invert_lanes_kernel(
       if (q + kLpp * r < kap) M[r][kap] = -u[r] * inv;
     if (q == kap % kLpp) M[kap / kLpp][kap] = inv;
   }
+}
+
+template <int D, int RIDGE>
+__global__ __launch_bounds__(kInvBlock) void invert_lanes_kernel(
+    const double* __restrict__ S, int H, int W, int R, double eps,
+    double* __restrict__ mu_out, void* __restrict__ minv_void) {
+  using MT = typename std::conditional<RIDGE != 0, double, float>::type;
+  MT* __restrict__ minv_out = static_cast<MT*>(minv_void);
+  constexpr int NG = RIDGE ? D - 1 : D;
+  constexpr int K = NG + NG * (NG + 1) / 2;
+  constexpr int PD = D * (D + 1) / 2;
+  constexpr int NR = (D + kLpp - 1) / kLpp;  // rows per lane
+  const int q = threadIdx.x % kLpp;
+  const int pr = static_cast<int>(blockIdx.x) * (kInvBlock / kLpp) + static_cast<int>(threadIdx.x) / kLpp;
+  // lanes of a pixel past the image idle through the arithmetic on pixel 0
+  // and store nothing (the broadcasts need every lane of the quad)
+  const bool live = pr < H * W;
+  const int p = live ? pr : 0;
+  const int y = p / W;
+  const int x = p - y * W;
+  const double Np = static_cast<double>(window_count(x, y, W, H, R));
+  const double invN = 1.0 / Np;
+
+  // The block's window sums (64 pixels x K, contiguous) are copied to LDS
+  // first with coalesced direct-to-LDS loads; the recursion then reads them
+  // at LDS latency.
+  __shared__ double Ss[(kInvBlock / kLpp) * K];
+  {
+    const int p0 = static_cast<int>(blockIdx.x) * (kInvBlock / kLpp);
+    const int cnt = min(kInvBlock / kLpp, H * W - p0);
+    const int dwords = cnt * K * 2;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(S + static_cast<size_t>(p0) * K);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(Ss);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int base = wv * 64; base < dwords; base += kInvBlock) {
+      const int i = min(base + lane, dwords - 1);
+      __builtin_amdgcn_global_load_lds(src + i, dst + base, 4, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  const double* s = Ss + (static_cast<int>(threadIdx.x) / kLpp) * K;
+
+  // one reciprocal per pixel; every entry is then formed with products only
+  auto A = [&](int i, int j) -> double {
+    if (!RIDGE) {
+      const double mi = s[i] * invN, mj = s[j] * invN;
+      return fma(s[NG + packed_index(i, j, NG)], invN, -mi * mj) + (i == j ? eps : 0.0);
+    }
+    if (i == 0) return (j == 0) ? Np + eps : s[j - 1];
+    return s[NG + packed_index(i - 1, j - 1, NG)] + (i == j ? eps : 0.0);
+  };
+
+  double M[NR][D];
+  quad_bordered_inverse<D>(A, q, M);
   if (!live) return;
   if (!RIDGE && q == 0) {
 #pragma unroll
@@ -427,6 +438,47 @@ __global__ __launch_bounds__(kInvBlock) void invert_lanes_kernel(
 #pragma unroll
       for (int j = 0; j < D; ++j)
         if (j >= i) o[base + j] = static_cast<MT>(M[r][j]);
+    }
+  }
+}
+
+// Dense batched form for D >= 11: the quad recursion above on matrices staged
+// in LDS (16 per block), full D x D inverse written out.
+constexpr int kSpdPerBlock = 16;
+
+template <int D>
+__global__ __launch_bounds__(kSpdPerBlock * kLpp) void spd_inverse_lanes_kernel(
+    const double* __restrict__ a, double* __restrict__ out, int count) {
+  constexpr int NR = (D + kLpp - 1) / kLpp;
+  __shared__ double sa[kSpdPerBlock * D * D];
+  const int b0 = static_cast<int>(blockIdx.x) * kSpdPerBlock;
+  {
+    const int cnt = min(kSpdPerBlock, count - b0);
+    const int dwords = cnt * D * D * 2;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a + static_cast<size_t>(b0) * D * D);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(sa);
+    const int lane = threadIdx.x & 63;
+    for (int base = 0; base < dwords; base += 64) {
+      const int i = min(base + lane, dwords - 1);
+      __builtin_amdgcn_global_load_lds(src + i, dst + base, 4, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  const int q = threadIdx.x % kLpp;
+  const int m = static_cast<int>(threadIdx.x) / kLpp;
+  const bool live = b0 + m < count;
+  const double* A_ = sa + (live ? m : 0) * D * D;
+  double M[NR][D];
+  quad_bordered_inverse<D>([&](int i, int j) { return A_[i * D + j]; }, q, M);
+  if (!live) return;
+  double* O = out + static_cast<size_t>(b0 + m) * D * D;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = q + kLpp * r;
+    if (i < D) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) O[i * D + j] = M[r][j];
     }
   }
 }
@@ -588,7 +640,14 @@ hipError_t launch_spd_inverse(const double* a, double* minv, int D, int count, h
   switch (D) {
 #define HGF_SPD(d)                                                                        \
   case d:                                                                                 \
-    hipLaunchKernelGGL(spd_inverse_kernel<d>, dim3(blocks), dim3(64), 0, s, a, minv, count); \
+    if constexpr (d >= 11) {                                                              \
+      const unsigned lb = static_cast<unsigned>((count + kSpdPerBlock - 1) / kSpdPerBlock); \
+      hipLaunchKernelGGL(spd_inverse_lanes_kernel<d>, dim3(lb), dim3(kSpdPerBlock * kLpp), 0, \
+                         s, a, minv, count);                                              \
+    } else {                                                                              \
+      hipLaunchKernelGGL(spd_inverse_kernel<d>, dim3(blocks), dim3(64), 0, s, a, minv,     \
+                         count);                                                          \
+    }                                                                                     \
     return hipGetLastError();
     HGF_SPD(1)
     HGF_SPD(2)

@@ -114,6 +114,7 @@ RIDGE_CASES = [
     W("ridge_gray_n1_r2", height=25, width=19, guide_channels=1, degree=1, labels=6, radius=2,
       eps=0.01, seed=33),
     W("ridge_n9_r9", height=48, width=66, degree=2, labels=20, radius=9, eps=0.05, seed=34),
+    W("ridge_n19_r4", height=30, width=44, degree=3, labels=20, radius=4, eps=0.05, seed=35),
 ]
 
 
@@ -137,7 +138,7 @@ def test_box_sum_bit_exact(shape, r):
     np.testing.assert_array_equal(out.cpu().numpy(), O.box_sum(x, r).astype(np.float32))
 
 
-@pytest.mark.parametrize("D", [1, 2, 3, 7, 10, 19, 20])
+@pytest.mark.parametrize("D", [1, 2, 3, 7, 10, 11, 13, 16, 19, 20])
 def test_spd_inverse_matches_lu(D):
     say(f"spd inverse D={D}")
     rng = np.random.default_rng(D)
