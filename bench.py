@@ -99,7 +99,7 @@ def roofline_of(name, model, ms_per_launch, traffic):
 
 def measured_traffic(workload: str, stage: str):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel sources; else None."""
+    were taken on the current sources of that kernel; else None."""
     path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -107,10 +107,9 @@ def measured_traffic(workload: str, stage: str):
         rec = json.load(open(path))
     except Exception:
         return None
-    if rec.get("source_hash") != source_hash():
-        return None
-    k = rec.get("kernels", {}).get(KERNEL_NAMES.get(stage, ""), None)
-    if not k:
+    name = KERNEL_NAMES.get(stage, "")
+    k = rec.get("kernels", {}).get(name, None)
+    if not k or k.get("source_hash") != source_hash(name):
         return None
     return k.get("hbm_bytes_per_launch")
 

@@ -31,15 +31,31 @@ HIPFLAGS = [
 ]
 
 
-def source_hash() -> str:
-    """Short hash of the kernel sources (identifies the code a measurement was taken on)."""
+# Sources that define each strip kernel and the launch geometry it runs with.
+_COMMON = ("hgf_device.hpp", "hgf_launch.hpp", "hgf_api.hip", "runtime.hpp")
+KERNEL_SOURCES = {
+    "coef_kernel": ("coef.hpp", "coef_n") + _COMMON,
+    "out_kernel": ("out.hpp", "out_n", "out.hip") + _COMMON,
+    "moments_kernel": ("guide.hip",) + _COMMON,
+    "invert_kernel": ("guide.hip",) + _COMMON,
+    "invert_lanes_kernel": ("guide.hip",) + _COMMON,
+}
+
+
+def source_hash(kernel: str | None = None) -> str:
+    """Short hash of the kernel sources (identifies the code a measurement was
+    taken on): all of them, or the files that define one kernel."""
     import hashlib
     h = hashlib.sha256()
+    prefixes = KERNEL_SOURCES.get(kernel) if kernel else None
     for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            with open(os.path.join(CSRC, f), "rb") as fh:
-                h.update(fh.read())
+        if not f.endswith((".hip", ".hpp")):
+            continue
+        if prefixes is not None and not any(f == p or f.startswith(p) for p in prefixes):
+            continue
+        h.update(f.encode())
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -120,11 +120,12 @@ def counters(fetch_dir: str, write_dir: str, out: str, workload: str, command: s
             "fetch_kib_raw": f_avg, "write_kib_raw": w_avg,
             "hbm_bytes_per_launch": 1024.0 * (f_avg * f_cal + w_avg * w_cal),
         }
-    # bench.py looks kernels up by their template name without arguments
+    # bench.py looks kernels up by their template name without arguments; each
+    # carries the hash of the sources that define it
     by_family = {}
     for k, v in kernels.items():
         fam = k.split("<")[0]
-        by_family.setdefault(fam, v)
+        by_family.setdefault(fam, dict(v, source_hash=source_hash(fam)))
     rec = {"workload": workload, "source_hash": source_hash(), "command": command,
            "fetch_factor": f_cal, "write_factor": w_cal,
            "calibration": "fill of 1 GiB (WRITE_SIZE) and sum over 1 GiB (FETCH_SIZE)",

@@ -294,3 +294,19 @@ def test_full_size_sampled(ctx, name):
     # properties that hold at every pixel: labels are the argmin of the returned costs
     assert np.array_equal(lab, np.argmin(Z.astype(np.float32), axis=2))
     assert np.isfinite(Z).all()
+
+
+def test_nan_costs_do_not_crash(ctx):
+    """Non-finite inputs have no defined result (the running sums carry a NaN on
+    down the strip), but the call must complete, keep every label in range
+    (NaN keys sort above every number) and leave later calls unaffected."""
+    w = CASES[0]
+    say("nan costs")
+    guide, cost = synth.make_workload(w)
+    bad = cost.copy()
+    bad[5, 7, :] = np.nan
+    bad[20, 30, 3] = np.inf
+    Z, lab = gpu_filter(ctx, guide, bad, w)
+    assert np.all((lab >= 0) & (lab < w.labels))
+    Z2, lab2 = gpu_filter(ctx, guide, cost, w)
+    check(Z2, lab2, oracle_filter(guide, cost, w), cost, "clean call after non-finite input")
