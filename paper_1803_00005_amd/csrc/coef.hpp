@@ -36,6 +36,11 @@ namespace hgf {
 // faster (the solves of a chunk start sooner).
 constexpr int coef_lds_bytes(int nch) { return nch <= 10 ? 120 * 1024 : 50 * 1024; }
 
+// Waves per block: one per channel group, rounded up to a multiple of the
+// four SIMDs of a CU from eight groups on, so that the solves (shared by all
+// waves) spread evenly over the SIMDs; the extra waves skip the box sums.
+constexpr int coef_block_waves(int nw) { return nw >= 8 ? (nw + 3) / 4 * 4 : nw; }
+
 template <int NCH, int SOUT>
 constexpr int coef_column_chunk() {
   int oc = coef_lds_bytes(NCH) / (NCH * 64 * 4);
@@ -51,7 +56,9 @@ template <int SIGN, bool CHECK, int CPW, int NCH, int SIN, typename TIN>
 __device__ __forceinline__ void coef_vrow(float (&vs)[CPW][SIN], const TIN* __restrict__ cost,
                                           int cost_ld, const float* __restrict__ g32, size_t P,
                                           int yy, int xsl, int W, int labc, int wv) {
-  const TIN* __restrict__ crow = cost + static_cast<size_t>(yy) * W * cost_ld;
+  const __amdgpu_buffer_rsrc_t crow = raw_rsrc(cost + static_cast<size_t>(yy) * W * cost_ld);
+  const int voff = labc * static_cast<int>(sizeof(TIN));
+  const int colb = cost_ld * static_cast<int>(sizeof(TIN));
   const float* __restrict__ grow = g32 + static_cast<size_t>(yy) * W + xsl;
 #pragma unroll
   for (int c0 = 0; c0 < SIN; c0 += kGrp) {
@@ -61,7 +68,7 @@ __device__ __forceinline__ void coef_vrow(float (&vs)[CPW][SIN], const TIN* __re
       if (c0 + c < SIN) {
         const int xr = xsl + c0 + c;
         const int xc = CHECK ? min(max(xr, 0), W - 1) : xr;
-        yv[c] = load_cost<TIN>(crow, static_cast<uint32_t>(xc) * static_cast<uint32_t>(cost_ld) + labc);
+        yv[c] = buf_load_cost<TIN>(crow, voff, xc * colb);
       }
     }
 #pragma unroll
@@ -97,21 +104,44 @@ __device__ __forceinline__ void stage_dwords(const uint32_t* __restrict__ src,
   }
 }
 
-// Dwords of LDS for the inverses and window means of one row of a strip,
-// rounded up to whole waves.
+// Dwords of LDS for the stored inverses (covariance form: the solve records
+// with the window means) of one row of a strip, rounded up to whole waves.
 template <int SOUT, int NG, int RIDGE>
 constexpr int coef_stage_dwords() {
-  constexpr int D = RIDGE ? NG + 1 : NG;
-  constexpr int PD = D * (D + 1) / 2;
-  constexpr int m = SOUT * PD * (RIDGE ? 2 : 1);
-  constexpr int u = RIDGE ? 0 : SOUT * NG * 2;
-  return (m + 63) / 64 * 64 + (u + 63) / 64 * 64;
+  constexpr int m = SOUT * minv_stride(RIDGE, NG) * (RIDGE ? 2 : 1);
+  return (m + 63) / 64 * 64;
 }
+
+// Reads element e of a float record at 16-byte unit `base` of an LDS array,
+// one 16-byte load per group of four elements.  Used with compile-time
+// indices in increasing order, so each load is issued once and its registers
+// are freed after the group.  The base index is held in a vector register so
+// that every load addresses it with an immediate offset.
+struct RecordReader {
+  const float4* __restrict__ lds4;
+  int base;
+  float4 cur;
+  int k = -1;
+  __device__ __forceinline__ RecordReader(const float4* a, int b) : lds4(a), base(b) {
+    asm volatile("" : "+v"(base));
+  }
+  __device__ __forceinline__ float operator()(int e) {
+    if (e / 4 != k) {
+      k = e / 4;
+      cur = lds4[base + k];
+    }
+    switch (e % 4) {
+      case 0: return cur.x;
+      case 1: return cur.y;
+      case 2: return cur.z;
+      default: return cur.w;
+    }
+  }
+};
 
 template <int R, int CPW, int NG, int RIDGE, typename TIN, int SIN, bool CHECK>
 __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cost_ld,
                                            const float* __restrict__ g32,
-                                           const double* __restrict__ mu,
                                            const void* __restrict__ minv_void,
                                            float* __restrict__ wsc, int H, int W, int xs,
                                            int x_out0, int y0, int y1, int labc, int wv, int lane,
@@ -119,6 +149,7 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
   constexpr int SOUT = SIN - 2 * R;
   constexpr int NCH = NG + 1;
   constexpr int NW = (NCH + CPW - 1) / CPW;
+  constexpr int NWB = coef_block_waves(NW);
   constexpr int D = RIDGE ? NG + 1 : NG;
   constexpr int PD = D * (D + 1) / 2;
   using MT = typename std::conditional<RIDGE != 0, double, float>::type;
@@ -144,28 +175,31 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
     return __builtin_amdgcn_readfirstlane(xsl);
   };
 
-  // this row's inverses [SOUT][PD] and (covariance form) window means
-  // [SOUT][NG], staged in LDS at the start of the row step
-  constexpr int M_DWORDS = SOUT * PD * (RIDGE ? 2 : 1);
+  // this row's stored inverses (covariance form: solve records [SOUT][RW]),
+  // staged in LDS at the start of the row step
+  constexpr int RW = minv_stride(RIDGE, NG);
   const MT* __restrict__ sm = reinterpret_cast<const MT*>(stage);
-  const double* __restrict__ su = reinterpret_cast<const double*>(stage + (M_DWORDS + 63) / 64 * 64);
 
   auto solve_store = [&](int x, int y, int q, int qx) {
     const size_t p = static_cast<size_t>(y) * W + x;
     float T[NCH];
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) T[ch] = lds[(q * NCH + ch) * 64 + lane];
-    const MT* __restrict__ mp = sm + qx * PD;
+    const MT* __restrict__ mp = sm + qx * RW;
     float* __restrict__ o = wsc + p * NCH * 64 + lane;
     if (!RIDGE) {
-      // c = (T - mu U) / N in float64, then the product a = M c in float32
-      const double invN = 1.0 / static_cast<double>(window_count(x, y, W, H, R));
-      const double U = static_cast<double>(T[0]);
+      // c = (T - mu U) / N, a = M c, b = U / N - a . mu, all float32: T is
+      // float32 already and each fused multiply-add rounds once, so c and b
+      // carry rounding errors of the order of T's own.
+      const float invN = __builtin_amdgcn_rcpf(static_cast<float>(window_count(x, y, W, H, R)));
+      const float U = T[0];
+      const float4* __restrict__ st4 = reinterpret_cast<const float4*>(stage);
+      RecordReader rd(st4, qx * (RW / 4));
       float c[NG];
       float av[NG];
 #pragma unroll
       for (int i = 0; i < NG; ++i) {
-        c[i] = static_cast<float>((static_cast<double>(T[i + 1]) - su[qx * NG + i] * U) * invN);
+        c[i] = fmaf(-rd(i), U, T[i + 1]) * invN;
         av[i] = 0.f;
       }
 #pragma unroll
@@ -173,18 +207,19 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
 #pragma unroll
         for (int j = i; j < NG; ++j) {
           const int qq = packed_index(i, j, D);
-          // bound the LDS reads in flight (each holds a register)
-          if (qq % MBLK == 0) __builtin_amdgcn_sched_barrier(0);
-          const float m = static_cast<float>(mp[qq]);
+          // bound the LDS reads in flight (each holds registers)
+          if ((NG + qq) % MBLK == 0) __builtin_amdgcn_sched_barrier(0);
+          const float m = rd(NG + qq);
           av[i] = fmaf(m, c[j], av[i]);
           if (j != i) av[j] = fmaf(m, c[i], av[j]);
         }
       }
-      // intercept b = U / N - a . mu in float64
-      double b = U * invN;
+      __builtin_amdgcn_sched_barrier(0);
+      RecordReader rm(st4, qx * (RW / 4));
+      float b = U * invN;
 #pragma unroll
-      for (int i = 0; i < NG; ++i) b = fma(-static_cast<double>(av[i]), su[qx * NG + i], b);
-      o[0] = static_cast<float>(b);
+      for (int i = 0; i < NG; ++i) b = fmaf(-av[i], rm(i), b);
+      o[0] = b;
 #pragma unroll
       for (int i = 0; i < NG; ++i) o[(i + 1) * 64] = av[i];
     } else {
@@ -218,18 +253,18 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
   auto stage_row = [&](int y) {
     const int cnt = min(SOUT, W - x_out0);
     const size_t p0 = static_cast<size_t>(y) * W + x_out0;
-    stage_dwords<NW>(reinterpret_cast<const uint32_t*>(minv + p0 * PD), stage,
-                     cnt * PD * (RIDGE ? 2 : 1), wv, lane);
-    if (!RIDGE)
-      stage_dwords<NW>(reinterpret_cast<const uint32_t*>(mu + p0 * NG),
-                       stage + (M_DWORDS + 63) / 64 * 64, cnt * NG * 2, wv, lane);
+    stage_dwords<NWB>(reinterpret_cast<const uint32_t*>(minv + p0 * RW), stage,
+                     cnt * RW * (RIDGE ? 2 : 1), wv, lane);
   };
 
-  for (int yy = max(0, y0 - R); yy <= min(H - 1, y0 + R); ++yy)
-    coef_vrow<1, CHECK, CPW, NCH, SIN, TIN>(vs, cost, cost_ld, g32, P, yy, launder(), W, labc, wv);
+  // waves past the channel groups (wv >= NW) only stage and solve
+  const bool box_wave = NWB == NW || wv < NW;
+  if (box_wave)
+    for (int yy = max(0, y0 - R); yy <= min(H - 1, y0 + R); ++yy)
+      coef_vrow<1, CHECK, CPW, NCH, SIN, TIN>(vs, cost, cost_ld, g32, P, yy, launder(), W, labc, wv);
   for (int y = y0; y < y1; ++y) {
     stage_row(y);
-    if (y > y0) {
+    if (box_wave && y > y0) {
       if (y + R < H)
         coef_vrow<1, CHECK, CPW, NCH, SIN, TIN>(vs, cost, cost_ld, g32, P, y + R, launder(), W,
                                                labc, wv);
@@ -252,7 +287,7 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
 #pragma unroll
       for (int jj = 0; jj < OC; ++jj) {
         const int j = cb * OC + jj;
-        if (j < SOUT) {
+        if (box_wave && j < SOUT) {
           if (j > 0) {
 #pragma unroll
             for (int k = 0; k < CPW; ++k) {
@@ -274,7 +309,7 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
       if (cb == 0) __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       const int cnt = min(OC, SOUT - cb * OC);
-      for (int q = wv; q < cnt; q += NW) {
+      for (int q = wv; q < cnt; q += NWB) {
         const int x = x_out0 + cb * OC + q;
         if (x < W) solve_store(x, y, q, cb * OC + q);
       }
@@ -284,15 +319,16 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
 }
 
 template <int R, int CPW, int NG, int RIDGE, typename TIN, int SIN>
-__global__ __launch_bounds__(640) void coef_kernel(
+__global__ __launch_bounds__(768) void coef_kernel(
     const TIN* __restrict__ cost, int cost_ld, const float* __restrict__ g32,
-    const double* __restrict__ mu, const void* __restrict__ minv, float* __restrict__ ws,
+    const void* __restrict__ minv, float* __restrict__ ws,
     int H, int W, int label_count, int band_h, int strips, int bands) {
   constexpr int SOUT = SIN - 2 * R;
   constexpr int NCH = NG + 1;
   constexpr int OC = coef_column_chunk<NCH, SOUT>();
   __shared__ float lds[OC * NCH * 64];
-  __shared__ uint32_t stage[coef_stage_dwords<SOUT, NG, RIDGE>()];
+  __shared__ float4 stage4[coef_stage_dwords<SOUT, NG, RIDGE>() / 4];
+  uint32_t* stage = reinterpret_cast<uint32_t*>(stage4);
 
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -316,10 +352,10 @@ __global__ __launch_bounds__(640) void coef_kernel(
   const size_t P = static_cast<size_t>(H) * W;
   float* __restrict__ wsc = ws + static_cast<size_t>(chunk) * P * NCH * 64;
   if (xs >= 0 && xs + SIN <= W)
-    coef_strip<R, CPW, NG, RIDGE, TIN, SIN, false>(cost, cost_ld, g32, mu, minv, wsc, H, W, xs,
+    coef_strip<R, CPW, NG, RIDGE, TIN, SIN, false>(cost, cost_ld, g32, minv, wsc, H, W, xs,
                                                    x_out0, y0, y1, labc, wv, lane, lds, stage);
   else
-    coef_strip<R, CPW, NG, RIDGE, TIN, SIN, true>(cost, cost_ld, g32, mu, minv, wsc, H, W, xs,
+    coef_strip<R, CPW, NG, RIDGE, TIN, SIN, true>(cost, cost_ld, g32, minv, wsc, H, W, xs,
                                                   x_out0, y0, y1, labc, wv, lane, lds, stage);
 }
 
@@ -327,12 +363,12 @@ template <int R, int NG, int RIDGE, typename TIN>
 hipError_t coef_launch_t(const CoefLaunch& a, hipStream_t s) {
   constexpr int NCH = NG + 1;
   constexpr int CPW = NCH > 10 ? 2 : 1;
-  constexpr int NW = (NCH + CPW - 1) / CPW;
+  constexpr int NWB = coef_block_waves((NCH + CPW - 1) / CPW);
   constexpr int SIN = coef_strip_width(NG);
   const StripGrid& g = a.grid;
   const unsigned blocks = static_cast<unsigned>(g.strips * g.bands * g.chunks);
-  hipLaunchKernelGGL((coef_kernel<R, CPW, NG, RIDGE, TIN, SIN>), dim3(blocks), dim3(NW * 64), 0, s,
-                     static_cast<const TIN*>(a.cost), a.cost_ld, a.g32, a.mu, a.minv, a.ws, a.H,
+  hipLaunchKernelGGL((coef_kernel<R, CPW, NG, RIDGE, TIN, SIN>), dim3(blocks), dim3(NWB * 64), 0, s,
+                     static_cast<const TIN*>(a.cost), a.cost_ld, a.g32, a.minv, a.ws, a.H,
                      a.W, a.label_count, g.band_h, g.strips, g.bands);
   return hipGetLastError();
 }

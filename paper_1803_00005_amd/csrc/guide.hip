@@ -265,12 +265,20 @@ __global__ __launch_bounds__(64) void invert_kernel(
     }
     M[packed_index(kap, kap, D)] = inv;
   }
+  constexpr int RW = minv_stride(RIDGE, NG);
+  MT* __restrict__ rec = minv_out + static_cast<size_t>(p) * RW;
   if (!RIDGE) {
 #pragma unroll
-    for (int i = 0; i < NG; ++i) mu_out[static_cast<size_t>(p) * NG + i] = mu[i];
-  }
+    for (int i = 0; i < NG; ++i) {
+      mu_out[static_cast<size_t>(p) * NG + i] = mu[i];
+      rec[i] = static_cast<MT>(mu[i]);
+    }
 #pragma unroll
-  for (int q = 0; q < PD; ++q) minv_out[static_cast<size_t>(p) * PD + q] = static_cast<MT>(M[q]);
+    for (int q = NG + PD; q < RW; ++q) rec[q] = MT(0);
+  }
+  constexpr int M0 = RIDGE ? 0 : NG;
+#pragma unroll
+  for (int q = 0; q < PD; ++q) rec[M0 + q] = static_cast<MT>(M[q]);
 }
 
 // Large systems (D >= 11): the same recursion with the rows of M spread over
@@ -425,11 +433,18 @@ __global__ __launch_bounds__(kInvBlock) void invert_lanes_kernel(
   double M[NR][D];
   quad_bordered_inverse<D>(A, q, M);
   if (!live) return;
+  constexpr int RW = minv_stride(RIDGE, NG);
+  MT* __restrict__ rec = minv_out + static_cast<size_t>(p) * RW;
   if (!RIDGE && q == 0) {
 #pragma unroll
-    for (int i = 0; i < NG; ++i) mu_out[static_cast<size_t>(p) * NG + i] = s[i] * invN;
+    for (int i = 0; i < NG; ++i) {
+      mu_out[static_cast<size_t>(p) * NG + i] = s[i] * invN;
+      rec[i] = static_cast<MT>(s[i] * invN);
+    }
+#pragma unroll
+    for (int e = NG + PD; e < RW; ++e) rec[e] = MT(0);
   }
-  MT* __restrict__ o = minv_out + static_cast<size_t>(p) * PD;
+  MT* __restrict__ o = rec + (RIDGE ? 0 : NG);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int i = q + kLpp * r;

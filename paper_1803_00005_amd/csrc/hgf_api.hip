@@ -210,7 +210,8 @@ Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
   pl.off_mu = off;
   off = align_up(off + sizeof(double) * static_cast<size_t>(pl.P) * pl.n);
   pl.off_minv = off;
-  off = align_up(off + static_cast<size_t>(minv_elem_bytes(p->reg)) * pl.P * pl.PD);
+  off = align_up(off + static_cast<size_t>(minv_elem_bytes(p->reg)) * pl.P *
+                           minv_stride(p->reg, pl.n));
   pl.off_x = off;
   const size_t s_bytes = sizeof(double) * static_cast<size_t>(pl.P) * pl.K;
   const size_t ws_bytes = pl.ws_chunk_bytes * pl.chunks_per_launch;
@@ -375,7 +376,7 @@ hgf_status run_guide(hgf_context* ctx, const Plan& pl, const float* guide, void*
 
 hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int cost_ld, float* out,
                       int out_ld, unsigned long long* keys, int label_base, int count,
-                      const float* g32, const double* mu, const void* minv, float* wsbuf,
+                      const float* g32, const void* minv, float* wsbuf,
                       hipStream_t s) {
   const size_t esz = pl.bf16 ? 2 : 4;
   const int coef_target = tuned_target(ctx, kTuneCoef, pl);
@@ -388,7 +389,6 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
     ca.cost_bf16 = pl.bf16;
     ca.cost_ld = cost_ld;
     ca.g32 = g32;
-    ca.mu = mu;
     ca.minv = minv;
     ca.ws = wsbuf;
     ca.n = pl.n;
@@ -435,7 +435,7 @@ hgf_status run_filter(hgf_context* ctx, const Plan& pl, const float* guide, cons
     HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
   }
   st = run_labels(ctx, pl, cost, cost_ld, out, out_ld, keys, 0, pl.L, pl.g32(ws),
-                  at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv), at<float>(ws, pl.off_x),
+                  at<char>(ws, pl.off_minv), at<float>(ws, pl.off_x),
                   s);
   if (st != HGF_OK) return st;
   if (keys != nullptr) {
@@ -584,7 +584,7 @@ hgf_status hgf_guide_filter(hgf_context* ctx, hgf_guide* g, const void* cost_chu
     HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
   }
   const hgf_status st = run_labels(ctx, pl, cost_chunk, ldv, out_chunk, ldv, keys, label_begin,
-                                   label_count, pl.g32(base), at<double>(base, pl.off_mu),
+                                   label_count, pl.g32(base),
                                    at<char>(base, pl.off_minv), at<float>(base, pl.off_x), s);
   if (st != HGF_OK) return st;
   if (keys != nullptr) {
@@ -614,11 +614,15 @@ hgf_status hgf_guide_export(const hgf_guide* g, double* mu, void* minv, double* 
                            sizeof(double) * static_cast<size_t>(pl.P) * pl.n,
                            hipMemcpyDeviceToDevice, s),
             "export mu");
-  if (minv != nullptr)
-    HGF_TRY(hipMemcpyAsync(minv, at<char>(g->base, pl.off_minv),
-                           static_cast<size_t>(minv_elem_bytes(g->params.reg)) * pl.P * pl.PD,
-                           hipMemcpyDeviceToDevice, s),
+  if (minv != nullptr) {
+    // the packed triangle of each pixel, out of its stored record
+    const size_t eb = static_cast<size_t>(minv_elem_bytes(g->params.reg));
+    const size_t skip = g->params.reg == 0 ? static_cast<size_t>(pl.n) : 0;
+    HGF_TRY(hipMemcpy2DAsync(minv, eb * pl.PD, at<char>(g->base, pl.off_minv) + eb * skip,
+                             eb * minv_stride(g->params.reg, pl.n), eb * pl.PD,
+                             static_cast<size_t>(pl.P), hipMemcpyDeviceToDevice, s),
             "export minv");
+  }
   if (shift != nullptr)
     HGF_TRY(hipMemcpyAsync(shift, at<char>(g->base, pl.off_shift), sizeof(double) * pl.n,
                            hipMemcpyDeviceToDevice, s),

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace hgf {
 
 // Largest guidance channel count n the kernels are built for, and the largest
@@ -71,6 +73,31 @@ __device__ __forceinline__ float load_cost<uint16_t>(const uint16_t* p, size_t i
   return bf16_to_float(p[i]);
 }
 
+// Raw buffer resource over `base` (gfx9 descriptor word 3: 32-bit data
+// format, no swizzle; the record limit is not used for range checks here, the
+// kernels form in-range offsets only).  A buffer load takes a wave-uniform
+// byte offset in a scalar register and a per-lane byte offset in a vector
+// register, so addressing a column costs scalar instructions only.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, 0x00020000);
+}
+
+__device__ __forceinline__ float buf_load_f32(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ float buf_load_cost(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ float buf_load_cost<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return buf_load_f32(r, voff, soff);
+}
+template <>
+__device__ __forceinline__ float buf_load_cost<uint16_t>(__amdgpu_buffer_rsrc_t r, int voff,
+                                                         int soff) {
+  return bf16_to_float(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+
 // Order-preserving map of a float to uint32 (NaN canonicalised to +qNaN, which
 // sorts above +inf): a < b  <=>  ordered(a) < ordered(b).
 __device__ __forceinline__ uint32_t ordered_bits(float f) {
@@ -88,6 +115,28 @@ __device__ __forceinline__ float ordered_to_float(uint32_t u) {
 __device__ __forceinline__ unsigned long long wta_key(float z, int label) {
   return (static_cast<unsigned long long>(ordered_bits(z)) << 32) |
          static_cast<unsigned long long>(static_cast<uint32_t>(label));
+}
+
+// Minimum over the 64 lanes of a wave, the same value in every lane: DPP
+// butterflies within each row of 16 lanes, then the four row minima.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  constexpr int kQuadSwap1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);
+  constexpr int kQuadSwap2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+  constexpr int kRowRor4 = 0x124;
+  constexpr int kRowRor8 = 0x128;
+  auto dpp = [](uint32_t x, auto ctrl) {
+    return static_cast<uint32_t>(
+        __builtin_amdgcn_mov_dpp(static_cast<int>(x), decltype(ctrl)::value, 0xf, 0xf, false));
+  };
+  v = min(v, dpp(v, std::integral_constant<int, kQuadSwap1>()));
+  v = min(v, dpp(v, std::integral_constant<int, kQuadSwap2>()));
+  v = min(v, dpp(v, std::integral_constant<int, kRowRor4>()));
+  v = min(v, dpp(v, std::integral_constant<int, kRowRor8>()));
+  const uint32_t a = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 0));
+  const uint32_t b = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 16));
+  const uint32_t c = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 32));
+  const uint32_t d = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 48));
+  return min(min(a, b), min(c, d));
 }
 
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {

@@ -52,14 +52,29 @@ hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
 // a2: window sums of G_i and G_i G_j (i <= j), float64 [P][K], K = n + n(n+1)/2.
 hipError_t launch_moments(const double* g64, int n, int H, int W, int R,
                           int target_blocks, double* S, hipStream_t s);
-// a3: per-pixel window mean mu [P][n] (covariance form) and the packed inverse
-// [P][D(D+1)/2] by the bordering recursion of Prop. 1, computed in float64 and
-// stored as float32 (covariance form) or float64 (ridge form).
+// a3: per-pixel window mean mu [P][n] (float64, covariance form) and the
+// per-pixel inverse by the bordering recursion of Prop. 1, computed in
+// float64.  Covariance form: a float32 solve record per pixel (below); ridge
+// form: the packed upper triangle [P][D(D+1)/2] in float64.
 hipError_t launch_invert(const double* S, int n, int H, int W, int R, double eps,
                          int reg, double* mu, void* minv, hipStream_t s);
 
 // Bytes per stored inverse element.
 constexpr int minv_elem_bytes(int reg) { return reg == 0 ? 4 : 8; }
+
+// Covariance-form solve record of one pixel, float32: the window mean
+// mu_1..mu_n, then the packed upper triangle of M_p (n(n+1)/2 entries, row by
+// row), zero-padded to a multiple of four floats so that the record can be
+// read with 16-byte loads.
+__host__ __device__ constexpr int cov_record_floats(int n) {
+  return (n + n * (n + 1) / 2 + 3) / 4 * 4;
+}
+
+// Elements per pixel of the stored inverse: the covariance record, or the
+// packed float64 triangle of the ridge form.
+__host__ __device__ constexpr int minv_stride(int reg, int n) {
+  return reg == 0 ? cov_record_floats(n) : (n + 1) * (n + 2) / 2;
+}
 
 // Logical block index of hardware block `bid` of `nb`: consecutive hardware
 // blocks are dispatched round-robin over the 8 XCDs, so this hands each XCD a
@@ -77,7 +92,6 @@ struct CoefLaunch {
   int cost_bf16;
   int cost_ld;
   const float* g32;     // planar [n+1][P], channel 0 = 1, padded
-  const double* mu;     // [P][n]
   const void* minv;     // [P][PD] float32 (covariance) or float64 (ridge)
   float* ws;            // [chunks][P][n+1][64]
   int n, H, W, R, reg;

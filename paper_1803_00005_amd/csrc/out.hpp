@@ -43,8 +43,10 @@ template <int SA, int SS, bool CHECK, int CPW, int NCH, int SIN, int GRP>
 __device__ __forceinline__ void out_vrow(float (&vs)[CPW][SIN], const float* __restrict__ wsc,
                                          int ya, int ys, int xsl, int W, int wv, int lane) {
   const size_t stride = static_cast<size_t>(W) * NCH * 64;
-  const float* __restrict__ ra = wsc + static_cast<size_t>(SA != 0 ? ya : 0) * stride;
-  const float* __restrict__ rs = wsc + static_cast<size_t>(SS != 0 ? ys : 0) * stride;
+  // (buffer loads with scalar column offsets measured slower here than
+  // global loads with vector addresses)
+  const float* __restrict__ ga = wsc + static_cast<size_t>(SA != 0 ? ya : 0) * stride;
+  const float* __restrict__ gs = wsc + static_cast<size_t>(SS != 0 ? ys : 0) * stride;
 #pragma unroll
   for (int c0 = 0; c0 < SIN; c0 += GRP) {
     float e[CPW][GRP];
@@ -58,8 +60,8 @@ __device__ __forceinline__ void out_vrow(float (&vs)[CPW][SIN], const float* __r
         for (int k = 0; k < CPW; ++k) {
           const int ch = (NCH % CPW == 0) ? wv * CPW + k : min(wv * CPW + k, NCH - 1);
           const uint32_t off = (static_cast<uint32_t>(xc) * NCH + ch) * 64u + lane;
-          if (SA != 0) e[k][c] = ra[off];
-          if (SS != 0) l[k][c] = rs[off];
+          if (SA != 0) e[k][c] = ga[off];
+          if (SS != 0) l[k][c] = gs[off];
         }
       }
     }
@@ -190,8 +192,15 @@ __device__ __forceinline__ void out_strip(const float* __restrict__ wsc,
           const float zf = static_cast<float>(z);
           if (out != nullptr && lab_ok) out[p * out_ld + lab] = zf;
           if (keys != nullptr) {
-            unsigned long long key = lab_ok ? wta_key(zf, label_base + lab) : ~0ull;
-            key = wave_min_u64(key);
+            // lowest ordered cost of the 64 labels, then the lowest lane
+            // holding it (labels increase with the lane)
+            const uint32_t u = lab_ok ? ordered_bits(zf) : 0xffffffffu;
+            const uint32_t m = wave_min_u32(u);
+            const int first = __builtin_ctzll(__ballot(u == m));
+            // both halves are wave-uniform; say so, so the atomic is issued once
+            const uint32_t hi = __builtin_amdgcn_readfirstlane(m);
+            const uint32_t lo = __builtin_amdgcn_readfirstlane(label_base + (lab - lane) + first);
+            const unsigned long long key = (static_cast<unsigned long long>(hi) << 32) | lo;
             if (lane == 0) atomicMin(&keys[p], key);
           }
         }

@@ -139,7 +139,7 @@ hgf_status run_guide(hgf_context* ctx, const Plan& pl, const float* guide, void*
                      hipStream_t s);
 hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int cost_ld, float* out,
                       int out_ld, unsigned long long* keys, int label_base, int count,
-                      const float* g32, const double* mu, const void* minv, float* wsbuf,
+                      const float* g32, const void* minv, float* wsbuf,
                       hipStream_t s);
 // Whole image: guide + labels + winner-takes-all into `labels`.
 hgf_status run_filter(hgf_context* ctx, const Plan& pl, const float* guide, const void* cost,

@@ -39,7 +39,7 @@ hgf_status time_path(hgf_context* ctx, const Plan& pl, const float* guide, const
       break;
     }
     st = run_labels(ctx, pl, cost, cost_ld, out, out_ld, keys, 0, pl.L, pl.g32(ws),
-                    at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv), at<float>(ws, pl.off_x),
+                    at<char>(ws, pl.off_minv), at<float>(ws, pl.off_x),
                     s);
   }
   const hgf_status st2 = hgf_stage_times(ctx, ms, nullptr, HGF_NUM_STAGES);
