@@ -41,9 +41,16 @@ constexpr int coef_lds_bytes(int nch) { return nch <= 10 ? 120 * 1024 : 50 * 102
 // waves) spread evenly over the SIMDs; the extra waves skip the box sums.
 constexpr int coef_block_waves(int nw) { return nw >= 8 ? (nw + 3) / 4 * 4 : nw; }
 
-template <int NCH, int SOUT>
+// LDS of a block besides the transposed window sums: the staged inverses of
+// one row and two staged cost rows.
+template <int SOUT, int SIN, int NG, int RIDGE>
+constexpr int coef_fixed_lds_bytes();
+
+template <int NCH, int SOUT, int SIN, int RIDGE>
 constexpr int coef_column_chunk() {
-  int oc = coef_lds_bytes(NCH) / (NCH * 64 * 4);
+  constexpr int avail = 160 * 1024 - coef_fixed_lds_bytes<SOUT, SIN, NCH - 1, RIDGE>();
+  constexpr int budget = coef_lds_bytes(NCH) < avail ? coef_lds_bytes(NCH) : avail;
+  int oc = budget / (NCH * 64 * 4);
   if (oc > SOUT) oc = SOUT;
   if (oc < 1) oc = 1;
   const int ncb = (SOUT + oc - 1) / oc;
@@ -89,6 +96,117 @@ __device__ __forceinline__ void coef_vrow(float (&vs)[CPW][SIN], const TIN* __re
   }
 }
 
+// Cost rows pass through LDS: a slot holds the SIN state columns of one row,
+// 64 labels each, one 32-bit word per (column, label); a bfloat16 cost lands
+// in the low half of its word.  The copies are direct global-to-LDS loads
+// (no registers), issued cooperatively by all waves of the block one row
+// step ahead of their use, so the vertical update reads LDS instead of
+// waiting on global memory.
+template <bool CHECK, int SIN, int NWB, typename TIN>
+__device__ __forceinline__ void stage_cost_row(const TIN* __restrict__ cost, int cost_ld, int yy,
+                                               int xsl, int W, int labc, float* __restrict__ slot,
+                                               int wv) {
+  const TIN* __restrict__ row = cost + static_cast<size_t>(yy) * W * cost_ld;
+  for (int c = wv; c < SIN; c += NWB) {
+    const int xr = xsl + c;
+    const int xc = CHECK ? min(max(xr, 0), W - 1) : xr;
+    typedef const __attribute__((address_space(1))) void* gsrc_t;
+    typedef __attribute__((address_space(3))) void* ldst_t;
+    const gsrc_t src = (gsrc_t)(row + static_cast<size_t>(xc) * cost_ld + labc);
+    if constexpr (sizeof(TIN) == 2)
+      __builtin_amdgcn_global_load_lds(src, (ldst_t)(slot + c * 64), 2, 0, 0);
+    else
+      __builtin_amdgcn_global_load_lds(src, (ldst_t)(slot + c * 64), 4, 0, 0);
+  }
+}
+
+// The guidance rows of the same row steps: slot [NCH][64] floats, channel ch
+// holding columns xs .. xs + 63 of the row (one direct-to-LDS load per
+// channel; columns past the image read the padding around the planar
+// guidance or a neighbouring row, and get weight 0).
+template <int NCH, int NWB>
+__device__ __forceinline__ void stage_guide_row(const float* __restrict__ g32, size_t P, int yy,
+                                                int xsl, int W, float* __restrict__ slot, int wv,
+                                                int lane) {
+  typedef const __attribute__((address_space(1))) void* gsrc_t;
+  typedef __attribute__((address_space(3))) void* ldst_t;
+  for (int ch = wv; ch < NCH; ch += NWB) {
+    const float* src = g32 + static_cast<size_t>(ch) * P + static_cast<size_t>(yy) * W + xsl + lane;
+    __builtin_amdgcn_global_load_lds((gsrc_t)src, (ldst_t)(slot + ch * 64), 4, 0, 0);
+  }
+}
+
+template <typename TIN>
+__device__ __forceinline__ float lds_cost(const float* __restrict__ slot, int i) {
+  if constexpr (sizeof(TIN) == 2) {
+    return bf16_to_float(reinterpret_cast<const uint16_t*>(slot)[2 * i]);
+  } else {
+    return slot[i];
+  }
+}
+
+// One vertical window update of every state column from staged rows: SA (0,
+// +1) times the products G_ch Y of row ya (slot sa) and SS (0, +1, -1) times
+// those of row ys (slot ss).
+template <int SA, int SS, bool CHECK, int CPW, int NCH, int SIN, typename TIN>
+__device__ __forceinline__ void coef_vrow_lds(float (&vs)[CPW][SIN], const float* __restrict__ sa,
+                                              const float* __restrict__ ss,
+                                              const float4* __restrict__ g4, int xsl, int W,
+                                              int wv, int lane) {
+  // columns per group: LDS latency is short, so a small group suffices and
+  // keeps registers (and, with two channels, scalar registers for the
+  // guidance values) free
+  constexpr int G = 8 / CPW;
+  static_assert(G % 4 == 0 || SIN % 4 == 0, "guidance reads are 16-byte groups");
+  // the lane's word in a slot, held in one vector register: every read then
+  // addresses it with an immediate column offset
+  int il = lane;
+  asm volatile("" : "+v"(il));
+#pragma unroll
+  for (int c0 = 0; c0 < SIN; c0 += G) {
+    float ea[G], es[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      if (c0 + c < SIN) {
+        if (SA != 0) ea[c] = lds_cost<TIN>(sa, il + (c0 + c) * 64);
+        if (SS != 0) es[c] = lds_cost<TIN>(ss, il + (c0 + c) * 64);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CPW; ++k) {
+      const int ch = wv * CPW + k;
+      const int chc = (NCH % CPW == 0) ? ch : min(ch, NCH - 1);
+      // guidance of this channel at the group's columns: 16-byte broadcast
+      // reads from one vector-register base (slot 1 lies NCH * 16 units on)
+      int gb = chc * 16;
+      asm volatile("" : "+v"(gb));
+      float gav[G], gsv[G];
+#pragma unroll
+      for (int c4 = 0; c4 < G; c4 += 4) {
+        if (SA != 0) {
+          const float4 q = g4[gb + (c0 + c4) / 4];
+          gav[c4] = q.x; gav[c4 + 1] = q.y; gav[c4 + 2] = q.z; gav[c4 + 3] = q.w;
+        }
+        if (SS != 0) {
+          const float4 q = g4[gb + NCH * 16 + (c0 + c4) / 4];
+          gsv[c4] = q.x; gsv[c4 + 1] = q.y; gsv[c4 + 2] = q.z; gsv[c4 + 3] = q.w;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        if (c0 + c < SIN) {
+          const int xr = xsl + c0 + c;
+          const bool ok = ((NCH % CPW == 0) || ch < NCH) && (!CHECK || (xr >= 0 && xr < W));
+          float& v = vs[k][c0 + c];
+          if (SA != 0) v = fmaf(ok ? gav[c] : 0.f, ea[c], v);
+          if (SS != 0) v = fmaf(ok ? (SS > 0 ? gsv[c] : -gsv[c]) : 0.f, es[c], v);
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // Copy `dwords` consecutive dwords from global memory into LDS without
 // passing through registers (global_load_lds, asynchronous: the copy is
 // complete after the issuing wave's vmcnt reaches zero, visible to the other
@@ -110,6 +228,11 @@ template <int SOUT, int NG, int RIDGE>
 constexpr int coef_stage_dwords() {
   constexpr int m = SOUT * minv_stride(RIDGE, NG) * (RIDGE ? 2 : 1);
   return (m + 63) / 64 * 64;
+}
+
+template <int SOUT, int SIN, int NG, int RIDGE>
+constexpr int coef_fixed_lds_bytes() {
+  return coef_stage_dwords<SOUT, NG, RIDGE>() * 4 + 2 * SIN * 64 * 4 + 2 * (NG + 1) * 64 * 4;
 }
 
 // Reads element e of a float record at 16-byte unit `base` of an LDS array,
@@ -145,7 +268,8 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
                                            const void* __restrict__ minv_void,
                                            float* __restrict__ wsc, int H, int W, int xs,
                                            int x_out0, int y0, int y1, int labc, int wv, int lane,
-                                           float* __restrict__ lds, uint32_t* __restrict__ stage) {
+                                           float* __restrict__ lds, uint32_t* __restrict__ stage,
+                                           float* __restrict__ cbuf, float* __restrict__ gbuf) {
   constexpr int SOUT = SIN - 2 * R;
   constexpr int NCH = NG + 1;
   constexpr int NW = (NCH + CPW - 1) / CPW;
@@ -156,7 +280,7 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
   const MT* __restrict__ minv = static_cast<const MT*>(minv_void);
   // inverse elements read from LDS per scheduling block of the product
   constexpr int MBLK = RIDGE ? 8 : 16;
-  constexpr int OC = coef_column_chunk<NCH, SOUT>();
+  constexpr int OC = coef_column_chunk<NCH, SOUT, SIN, RIDGE>();
   constexpr int NCB = (SOUT + OC - 1) / OC;
   const size_t P = static_cast<size_t>(H) * W;
 
@@ -259,18 +383,53 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
 
   // waves past the channel groups (wv >= NW) only stage and solve
   const bool box_wave = NWB == NW || wv < NW;
-  if (box_wave)
-    for (int yy = max(0, y0 - R); yy <= min(H - 1, y0 + R); ++yy)
-      coef_vrow<1, CHECK, CPW, NCH, SIN, TIN>(vs, cost, cost_ld, g32, P, yy, launder(), W, labc, wv);
+  float* __restrict__ slot0 = cbuf;
+  float* __restrict__ slot1 = cbuf + SIN * 64;
+  float* __restrict__ gslot0 = gbuf;
+  float* __restrict__ gslot1 = gbuf + NCH * 64;
+  const float4* __restrict__ g40 = reinterpret_cast<const float4*>(gslot0);
+  // cost and guidance of row yy into slot pair 0 or 1
+  auto stage_cost = [&](int yy, int sl) {
+    stage_cost_row<CHECK, SIN, NWB, TIN>(cost, cost_ld, yy, launder(), W, labc,
+                                         sl ? slot1 : slot0, wv);
+    stage_guide_row<NCH, NWB>(g32, P, yy, launder(), W, sl ? gslot1 : gslot0, wv, lane);
+  };
+
+  // initial window of the band, rows y0 - R .. y0 + R, two rows per round
+  {
+    const int ra = max(0, y0 - R), rb = min(H - 1, y0 + R);
+    for (int yy = ra; yy <= rb; yy += 2) {
+      const bool two = yy + 1 <= rb;
+      stage_cost(yy, 0);
+      if (two) stage_cost(yy + 1, 1);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (box_wave) {
+        if (two)
+          coef_vrow_lds<1, 1, CHECK, CPW, NCH, SIN, TIN>(vs, slot0, slot1, g40, launder(),
+                                                       W, wv, lane);
+        else
+          coef_vrow_lds<1, 0, CHECK, CPW, NCH, SIN, TIN>(vs, slot0, slot1, g40, launder(),
+                                                       W, wv, lane);
+      }
+      __syncthreads();
+    }
+  }
   for (int y = y0; y < y1; ++y) {
     stage_row(y);
+    // rows y + R (slot 0) and y - R - 1 (slot 1) were staged during the
+    // previous row step
     if (box_wave && y > y0) {
-      if (y + R < H)
-        coef_vrow<1, CHECK, CPW, NCH, SIN, TIN>(vs, cost, cost_ld, g32, P, y + R, launder(), W,
-                                               labc, wv);
-      if (y - R - 1 >= 0)
-        coef_vrow<-1, CHECK, CPW, NCH, SIN, TIN>(vs, cost, cost_ld, g32, P, y - R - 1, launder(),
-                                                W, labc, wv);
+      const bool a = y + R < H, sb = y - R - 1 >= 0;
+      if (a && sb)
+        coef_vrow_lds<1, -1, CHECK, CPW, NCH, SIN, TIN>(vs, slot0, slot1, g40, launder(), W,
+                                                        wv, lane);
+      else if (a)
+        coef_vrow_lds<1, 0, CHECK, CPW, NCH, SIN, TIN>(vs, slot0, slot1, g40, launder(),
+                                                       W, wv, lane);
+      else if (sb)
+        coef_vrow_lds<0, -1, CHECK, CPW, NCH, SIN, TIN>(vs, slot0, slot1, g40, launder(),
+                                                       W, wv, lane);
     }
     double hs[CPW];
 #pragma unroll
@@ -308,11 +467,19 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
       // the staged row must have landed before the barrier publishes it
       if (cb == 0) __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
+      if (cb == 0 && y + 1 < y1) {
+        // every wave is past its vertical update: stage the next row step's
+        // cost rows while the solves run
+        if (y + 1 + R < H) stage_cost(y + 1 + R, 0);
+        if (y - R >= 0) stage_cost(y - R, 1);
+      }
       const int cnt = min(OC, SOUT - cb * OC);
       for (int q = wv; q < cnt; q += NWB) {
         const int x = x_out0 + cb * OC + q;
         if (x < W) solve_store(x, y, q, cb * OC + q);
       }
+      // the staged cost rows must have landed before the row's last barrier
+      if (cb == NCB - 1) __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
     }
   }
@@ -325,9 +492,11 @@ __global__ __launch_bounds__(768) void coef_kernel(
     int H, int W, int label_count, int band_h, int strips, int bands) {
   constexpr int SOUT = SIN - 2 * R;
   constexpr int NCH = NG + 1;
-  constexpr int OC = coef_column_chunk<NCH, SOUT>();
+  constexpr int OC = coef_column_chunk<NCH, SOUT, SIN, RIDGE>();
   __shared__ float lds[OC * NCH * 64];
   __shared__ float4 stage4[coef_stage_dwords<SOUT, NG, RIDGE>() / 4];
+  __shared__ float cbuf[2 * SIN * 64];
+  __shared__ float4 gbuf4[2 * NCH * 16];
   uint32_t* stage = reinterpret_cast<uint32_t*>(stage4);
 
   const int lane = threadIdx.x & 63;
@@ -353,10 +522,12 @@ __global__ __launch_bounds__(768) void coef_kernel(
   float* __restrict__ wsc = ws + static_cast<size_t>(chunk) * P * NCH * 64;
   if (xs >= 0 && xs + SIN <= W)
     coef_strip<R, CPW, NG, RIDGE, TIN, SIN, false>(cost, cost_ld, g32, minv, wsc, H, W, xs,
-                                                   x_out0, y0, y1, labc, wv, lane, lds, stage);
+                                                   x_out0, y0, y1, labc, wv, lane, lds, stage,
+                                                   cbuf, reinterpret_cast<float*>(gbuf4));
   else
     coef_strip<R, CPW, NG, RIDGE, TIN, SIN, true>(cost, cost_ld, g32, minv, wsc, H, W, xs,
-                                                  x_out0, y0, y1, labc, wv, lane, lds, stage);
+                                                  x_out0, y0, y1, labc, wv, lane, lds, stage,
+                                                   cbuf, reinterpret_cast<float*>(gbuf4));
 }
 
 template <int R, int NG, int RIDGE, typename TIN>

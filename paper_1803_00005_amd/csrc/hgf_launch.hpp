@@ -26,7 +26,7 @@ StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_bloc
 // State columns per strip of the coefficient kernel: up to n = 9 one channel
 // per wave and 64 columns; above, two channels per wave and a narrower strip
 // so that ten waves fit the register file.
-constexpr int coef_strip_width(int n) { return n + 1 > 10 ? 38 : 64; }
+constexpr int coef_strip_width(int n) { return n + 1 > 10 ? 38 : (n + 1 == 10 ? 62 : 64); }
 // Output kernel: channels per wave (ten waves at most) and state columns per
 // strip for n guidance channels (two channels per wave leave room for 48).
 constexpr int out_channels_per_wave(int n) { return n + 1 > 10 ? 2 : 1; }
