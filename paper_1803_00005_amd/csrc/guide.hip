@@ -188,6 +188,100 @@ __global__ __launch_bounds__(256) void moments_kernel(
   }
 }
 
+// The same window sums for up to nine channels (K <= 54 moments), with the
+// lanes of one wave as the 64 state columns of the strip during the vertical
+// update: a lane loads the n guidance values of its column of the entering
+// and the leaving row (a few contiguous loads, all in flight together) and
+// updates the float64 running sums of all K moments of that column.  The
+// sums then pass through LDS, transposed to lanes = moments, for the
+// horizontal running sums and the coalesced stores of S[p][k].
+template <int R, int NG>
+__global__ __launch_bounds__(64) void moments_cols_kernel(
+    const double* __restrict__ g64, int H, int W, int band_h, int strips,
+    double* __restrict__ S) {
+  constexpr int K = NG + NG * (NG + 1) / 2;
+  constexpr int SOUT = kStrip - 2 * R;
+  constexpr int TS = kStrip + 1;  // LDS row stride of the transpose (doubles)
+  __shared__ double tr[K * TS];
+  const int lane = threadIdx.x;
+  const int bid = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int strip = __builtin_amdgcn_readfirstlane(bid % strips);
+  const int band = __builtin_amdgcn_readfirstlane(bid / strips);
+  const int x_out0 = strip * SOUT;
+  const int xs = x_out0 - R;
+  const int y0 = band * band_h;
+  const int y1 = min(H, y0 + band_h);
+  // this lane's state column; outside the image it reads a clamped column
+  // with weight 0
+  const int xr = xs + lane;
+  const int xc = min(max(xr, 0), W - 1);
+  const double w = (xr >= 0 && xr < W) ? 1.0 : 0.0;
+
+  double vs[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) vs[k] = 0.0;
+
+  auto load = [&](int yy, double (&g)[NG]) {
+    const double* __restrict__ src = g64 + (static_cast<size_t>(yy) * W + xc) * NG;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) g[i] = src[i];
+  };
+  // coefficient times the K moments of g (g_k, then g_i g_j, i <= j, in the
+  // packed order) added to the running sums
+  auto add = [&](const double (&g)[NG], double coef) {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) vs[i] = fma(coef, g[i], vs[i]);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const double ci = coef * g[i];
+#pragma unroll
+      for (int j = i; j < NG; ++j) {
+        const int k = NG + packed_index(i, j, NG);
+        vs[k] = fma(ci, g[j], vs[k]);
+      }
+    }
+  };
+  // add row ya (if a) and, with sign sgn_s, row ys (if sb); both rows' loads
+  // are issued first
+  auto update = [&](int ya, bool a, int ys, bool sb, double sgn_s) {
+    double ga[NG], gs[NG];
+    if (a) load(ya, ga);
+    if (sb) load(ys, gs);
+    if (a) add(ga, w);
+    if (sb) add(gs, sgn_s * w);
+  };
+
+  // initial window, two rows per round
+  {
+    const int ra = max(0, y0 - R), rb = min(H - 1, y0 + R);
+    for (int yy = ra; yy <= rb; yy += 2) update(yy, true, yy + 1, yy + 1 <= rb, 1.0);
+  }
+  for (int y = y0; y < y1; ++y) {
+    if (y > y0) update(y + R, y + R < H, y - R - 1, y - R - 1 >= 0, -1.0);
+    // transpose: lanes become moments
+#pragma unroll
+    for (int k = 0; k < K; ++k) tr[k * TS + lane] = vs[k];
+    __syncthreads();
+    if (lane < K) {
+      const double* __restrict__ row = tr + lane * TS;
+      // the output row origin is laundered so that the per-column store
+      // addresses are formed as they are used, not hoisted out of the loop
+      int ox = x_out0;
+      asm volatile("" : "+s"(ox));
+      double* __restrict__ srow = S + (static_cast<size_t>(y) * W + ox) * K + lane;
+      double hs = 0.0;
+#pragma unroll
+      for (int c = 0; c <= 2 * R; ++c) hs += row[c];
+#pragma unroll
+      for (int j = 0; j < SOUT; ++j) {
+        if (j > 0) hs += row[j + 2 * R] - row[j - 1];
+        if (x_out0 + j < W) srow[static_cast<size_t>(j) * K] = hs;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // a3: per-pixel inverse of the D x D window system by bordering, float64.
 //
@@ -564,9 +658,30 @@ hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
   return hipGetLastError();
 }
 
+template <int R, int NG>
+static hipError_t moments_cols(const double* g64, int H, int W, int target, double* S,
+                               hipStream_t s) {
+  StripGrid g = strip_grid(H, W, R, 1, target);
+  hipLaunchKernelGGL((moments_cols_kernel<R, NG>), dim3(static_cast<unsigned>(g.strips * g.bands)),
+                     dim3(64), 0, s, g64, H, W, g.band_h, g.strips, S);
+  return hipGetLastError();
+}
+
 template <int R>
 static hipError_t moments_r(const double* g64, int n, int H, int W, int target, double* S,
                            hipStream_t s) {
+  switch (n) {
+    case 1: return moments_cols<R, 1>(g64, H, W, target, S, s);
+    case 2: return moments_cols<R, 2>(g64, H, W, target, S, s);
+    case 3: return moments_cols<R, 3>(g64, H, W, target, S, s);
+    case 4: return moments_cols<R, 4>(g64, H, W, target, S, s);
+    case 5: return moments_cols<R, 5>(g64, H, W, target, S, s);
+    case 6: return moments_cols<R, 6>(g64, H, W, target, S, s);
+    case 7: return moments_cols<R, 7>(g64, H, W, target, S, s);
+    case 8: return moments_cols<R, 8>(g64, H, W, target, S, s);
+    case 9: return moments_cols<R, 9>(g64, H, W, target, S, s);
+    default: break;
+  }
   const int K = n + n * (n + 1) / 2;
   StripGrid g = strip_grid(H, W, R, (K + 255) / 256, target);
   dim3 grid(static_cast<unsigned>(g.strips * g.bands), static_cast<unsigned>((K + 255) / 256));
