@@ -99,111 +99,48 @@ __global__ __launch_bounds__(256) void guide_synth_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// a2: window sums of the K = n + n(n+1)/2 guidance moments.  Lanes are moment
-// channels; a wave walks down a band of rows over a strip of 64 state
-// columns, keeping float64 vertical running sums in registers (add the row
-// entering the window, subtract the row leaving it) and forming the
-// horizontal window sums in registers, so no cross-lane traffic is needed.
-// Output S[p][k], coalesced over k.
-// ---------------------------------------------------------------------------
-template <int R>
-__global__ __launch_bounds__(256) void moments_kernel(
-    const double* __restrict__ g64, int n, int K, int H, int W, int band_h, int strips,
-    double* __restrict__ S) {
-  constexpr int SOUT = kStrip - 2 * R;
-  const int lane = threadIdx.x & 63;
-  const int k = static_cast<int>(blockIdx.y) * 256 + threadIdx.x;
-  (void)lane;
-  const bool kok = k < K;
-  int ci = 0, cj = -1;
-  if (kok) {
-    if (k < n) {
-      ci = k;
-    } else {
-      int q = k - n, i = 0;
-      while (q >= n - i) { q -= n - i; ++i; }
-      ci = i;
-      cj = i + q;
-    }
-  }
-  const int bid = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
-  const int strip = __builtin_amdgcn_readfirstlane(bid % strips);
-  const int band = __builtin_amdgcn_readfirstlane(bid / strips);
-  const int x_out0 = strip * SOUT;
-  const int xs = x_out0 - R;
-  const int y0 = band * band_h;
-  const int y1 = min(H, y0 + band_h);
+// a2: window sums of the K = n + n(n+1)/2 guidance moments, float64, with
+// vertical running sums (add the row entering the window, subtract the row
+// leaving it) and horizontal running sums over strips of 64 state columns.
+// The lanes of a wave are the 64 state columns of the strip during the
+// vertical update: a lane loads the n guidance values of
+// its column of the entering and the leaving row (a few contiguous loads, all
+// in flight together) and updates the float64 running sums of the moments of
+// that column.  Up to nine channels one wave holds all K <= 54 moments; with
+// more, each of the block's waves holds KW consecutive moments (the waves
+// read the same columns, from L1).  The sums then pass through LDS,
+// transposed to lanes = moments, for the horizontal running sums and the
+// coalesced stores of S[p][k].
 
-  double vs[kStrip];
+// coef times the moments [K0, K0 + KW) of g (g_k, then g_i g_j, i <= j, in
+// the packed order) added to the running sums vs[k - K0]
+template <int NG, int K0, int KW>
+__device__ __forceinline__ void add_moments(double (&vs)[KW], const double (&g)[NG], double coef) {
 #pragma unroll
-  for (int c = 0; c < kStrip; ++c) vs[c] = 0.0;
-
-  // lanes past the last moment channel read channel 0 and never store
-  const int cic = kok ? ci : 0;
-  const int cjc = (kok && cj >= 0) ? cj : 0;
-  const double jone = (kok && cj >= 0) ? 0.0 : 1.0;
-
-  // Vertical update, kGrp columns of loads issued at a time; columns outside
-  // the image read a clamped pixel with weight 0.  The strip origin is
-  // laundered so per-column offsets are not hoisted out of the row loop.
-  auto acc_row = [&](int yy, double sgn) {
-    int xsl = __builtin_amdgcn_readfirstlane(xs);
-    asm volatile("" : "+s"(xsl));
-    xsl = __builtin_amdgcn_readfirstlane(xsl);
-    const double* __restrict__ row = g64 + static_cast<size_t>(yy) * W * n;
+  for (int i = 0; i < NG; ++i)
+    if (i >= K0 && i < K0 + KW) vs[i - K0] = fma(coef, g[i], vs[i - K0]);
 #pragma unroll
-    for (int c0 = 0; c0 < kStrip; c0 += kGrp) {
-      double gi[kGrp], gj[kGrp];
+  for (int i = 0; i < NG; ++i) {
+    const double ci = coef * g[i];
 #pragma unroll
-      for (int c = 0; c < kGrp; ++c) {
-        const int xc = min(max(xsl + c0 + c, 0), W - 1);
-        const uint32_t o = static_cast<uint32_t>(xc) * static_cast<uint32_t>(n);
-        gi[c] = row[o + cic];
-        gj[c] = row[o + cjc];
-      }
-#pragma unroll
-      for (int c = 0; c < kGrp; ++c) {
-        const int xr = xsl + c0 + c;
-        const double w = (xr >= 0 && xr < W) ? sgn : 0.0;
-        vs[c0 + c] = fma(w * gi[c], fma(gj[c], 1.0 - jone, jone), vs[c0 + c]);
-      }
-    }
-  };
-
-  for (int yy = max(0, y0 - R); yy <= min(H - 1, y0 + R); ++yy) acc_row(yy, 1.0);
-  for (int y = y0; y < y1; ++y) {
-    if (y > y0) {
-      if (y + R < H) acc_row(y + R, 1.0);
-      if (y - R - 1 >= 0) acc_row(y - R - 1, -1.0);
-    }
-    double hs = 0.0;
-#pragma unroll
-    for (int c = 0; c <= 2 * R; ++c) hs += vs[c];
-#pragma unroll
-    for (int j = 0; j < SOUT; ++j) {
-      if (j > 0) hs += vs[j + 2 * R] - vs[j - 1];
-      const int x = x_out0 + j;
-      if (x < W && kok) S[(static_cast<size_t>(y) * W + x) * K + k] = hs;
+    for (int j = i; j < NG; ++j) {
+      const int k = NG + packed_index(i, j, NG);
+      if (k >= K0 && k < K0 + KW) vs[k - K0] = fma(ci, g[j], vs[k - K0]);
     }
   }
 }
 
-// The same window sums for up to nine channels (K <= 54 moments), with the
-// lanes of one wave as the 64 state columns of the strip during the vertical
-// update: a lane loads the n guidance values of its column of the entering
-// and the leaving row (a few contiguous loads, all in flight together) and
-// updates the float64 running sums of all K moments of that column.  The
-// sums then pass through LDS, transposed to lanes = moments, for the
-// horizontal running sums and the coalesced stores of S[p][k].
-template <int R, int NG>
-__global__ __launch_bounds__(64) void moments_cols_kernel(
+template <int R, int NG, int KW>
+__global__ __launch_bounds__((NG + NG * (NG + 1) / 2 + KW - 1) / KW * 64) void moments_cols_kernel(
     const double* __restrict__ g64, int H, int W, int band_h, int strips,
     double* __restrict__ S) {
   constexpr int K = NG + NG * (NG + 1) / 2;
+  constexpr int NWM = (K + KW - 1) / KW;  // waves of the block
   constexpr int SOUT = kStrip - 2 * R;
   constexpr int TS = kStrip + 1;  // LDS row stride of the transpose (doubles)
   __shared__ double tr[K * TS];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int bid = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
   const int strip = __builtin_amdgcn_readfirstlane(bid % strips);
   const int band = __builtin_amdgcn_readfirstlane(bid / strips);
@@ -217,28 +154,27 @@ __global__ __launch_bounds__(64) void moments_cols_kernel(
   const int xc = min(max(xr, 0), W - 1);
   const double w = (xr >= 0 && xr < W) ? 1.0 : 0.0;
 
-  double vs[K];
+  double vs[KW];
 #pragma unroll
-  for (int k = 0; k < K; ++k) vs[k] = 0.0;
+  for (int k = 0; k < KW; ++k) vs[k] = 0.0;
 
   auto load = [&](int yy, double (&g)[NG]) {
     const double* __restrict__ src = g64 + (static_cast<size_t>(yy) * W + xc) * NG;
 #pragma unroll
     for (int i = 0; i < NG; ++i) g[i] = src[i];
   };
-  // coefficient times the K moments of g (g_k, then g_i g_j, i <= j, in the
-  // packed order) added to the running sums
+  // this wave's moments of g times coef added to its running sums
   auto add = [&](const double (&g)[NG], double coef) {
-#pragma unroll
-    for (int i = 0; i < NG; ++i) vs[i] = fma(coef, g[i], vs[i]);
-#pragma unroll
-    for (int i = 0; i < NG; ++i) {
-      const double ci = coef * g[i];
-#pragma unroll
-      for (int j = i; j < NG; ++j) {
-        const int k = NG + packed_index(i, j, NG);
-        vs[k] = fma(ci, g[j], vs[k]);
-      }
+    static_assert(NWM <= 8, "at most eight moment waves");
+    switch (wv) {
+      case 0: add_moments<NG, 0 * KW, KW>(vs, g, coef); break;
+      case 1: if constexpr (NWM > 1) add_moments<NG, 1 * KW, KW>(vs, g, coef); break;
+      case 2: if constexpr (NWM > 2) add_moments<NG, 2 * KW, KW>(vs, g, coef); break;
+      case 3: if constexpr (NWM > 3) add_moments<NG, 3 * KW, KW>(vs, g, coef); break;
+      case 4: if constexpr (NWM > 4) add_moments<NG, 4 * KW, KW>(vs, g, coef); break;
+      case 5: if constexpr (NWM > 5) add_moments<NG, 5 * KW, KW>(vs, g, coef); break;
+      case 6: if constexpr (NWM > 6) add_moments<NG, 6 * KW, KW>(vs, g, coef); break;
+      default: if constexpr (NWM > 7) add_moments<NG, 7 * KW, KW>(vs, g, coef); break;
     }
   };
   // add row ya (if a) and, with sign sgn_s, row ys (if sb); both rows' loads
@@ -260,15 +196,17 @@ __global__ __launch_bounds__(64) void moments_cols_kernel(
     if (y > y0) update(y + R, y + R < H, y - R - 1, y - R - 1 >= 0, -1.0);
     // transpose: lanes become moments
 #pragma unroll
-    for (int k = 0; k < K; ++k) tr[k * TS + lane] = vs[k];
+    for (int k = 0; k < KW; ++k)
+      if (wv * KW + k < K) tr[(wv * KW + k) * TS + lane] = vs[k];
     __syncthreads();
-    if (lane < K) {
-      const double* __restrict__ row = tr + lane * TS;
+    const int kk = static_cast<int>(threadIdx.x);
+    if (kk < K) {
+      const double* __restrict__ row = tr + kk * TS;
       // the output row origin is laundered so that the per-column store
       // addresses are formed as they are used, not hoisted out of the loop
       int ox = x_out0;
       asm volatile("" : "+s"(ox));
-      double* __restrict__ srow = S + (static_cast<size_t>(y) * W + ox) * K + lane;
+      double* __restrict__ srow = S + (static_cast<size_t>(y) * W + ox) * K + kk;
       double hs = 0.0;
 #pragma unroll
       for (int c = 0; c <= 2 * R; ++c) hs += row[c];
@@ -661,9 +599,14 @@ hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
 template <int R, int NG>
 static hipError_t moments_cols(const double* g64, int H, int W, int target, double* S,
                                hipStream_t s) {
+  constexpr int K = NG + NG * (NG + 1) / 2;
+  // one wave for up to 64 moments; above, eight waves of up to 27 moments
+  constexpr int KW = K <= 64 ? K : (K + 7) / 8;
+  constexpr int NWM = (K + KW - 1) / KW;
   StripGrid g = strip_grid(H, W, R, 1, target);
-  hipLaunchKernelGGL((moments_cols_kernel<R, NG>), dim3(static_cast<unsigned>(g.strips * g.bands)),
-                     dim3(64), 0, s, g64, H, W, g.band_h, g.strips, S);
+  hipLaunchKernelGGL((moments_cols_kernel<R, NG, KW>),
+                     dim3(static_cast<unsigned>(g.strips * g.bands)), dim3(NWM * 64), 0, s, g64,
+                     H, W, g.band_h, g.strips, S);
   return hipGetLastError();
 }
 
@@ -680,15 +623,9 @@ static hipError_t moments_r(const double* g64, int n, int H, int W, int target, 
     case 7: return moments_cols<R, 7>(g64, H, W, target, S, s);
     case 8: return moments_cols<R, 8>(g64, H, W, target, S, s);
     case 9: return moments_cols<R, 9>(g64, H, W, target, S, s);
-    default: break;
+    case 19: return moments_cols<R, 19>(g64, H, W, target, S, s);
+    default: return hipErrorNotSupported;
   }
-  const int K = n + n * (n + 1) / 2;
-  StripGrid g = strip_grid(H, W, R, (K + 255) / 256, target);
-  dim3 grid(static_cast<unsigned>(g.strips * g.bands), static_cast<unsigned>((K + 255) / 256));
-  const int threads = K >= 256 ? 256 : ((K + 63) / 64) * 64;
-  hipLaunchKernelGGL(moments_kernel<R>, grid, dim3(threads), 0, s, g64, n, K, H, W, g.band_h,
-                     g.strips, S);
-  return hipGetLastError();
 }
 
 hipError_t launch_moments(const double* g64, int n, int H, int W, int R, int target,
