@@ -388,29 +388,49 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
   float* __restrict__ gslot0 = gbuf;
   float* __restrict__ gslot1 = gbuf + NCH * 64;
   const float4* __restrict__ g40 = reinterpret_cast<const float4*>(gslot0);
-  // cost and guidance of row yy into slot pair 0 or 1
+  // cost and guidance of row yy into a cost slot and a guidance slot
+  auto stage_to = [&](int yy, float* cs, float* gs) {
+    stage_cost_row<CHECK, SIN, NWB, TIN>(cost, cost_ld, yy, launder(), W, labc, cs, wv);
+    stage_guide_row<NCH, NWB>(g32, P, yy, launder(), W, gs, wv, lane);
+  };
   auto stage_cost = [&](int yy, int sl) {
-    stage_cost_row<CHECK, SIN, NWB, TIN>(cost, cost_ld, yy, launder(), W, labc,
-                                         sl ? slot1 : slot0, wv);
-    stage_guide_row<NCH, NWB>(g32, P, yy, launder(), W, sl ? gslot1 : gslot0, wv, lane);
+    stage_to(yy, sl ? slot1 : slot0, sl ? gslot1 : gslot0);
   };
 
-  // initial window of the band, rows y0 - R .. y0 + R, two rows per round
+  // Initial window of the band, rows y0 - R .. y0 + R.  The window-sum area
+  // is free until the first row's horizontal sums, so it holds XS more staged
+  // rows (their cost slots first, then their guidance slots, each guidance
+  // slot NCH * 64 floats after the previous one like the two main slots):
+  // 2 + XS rows per round, consumed in pairs.
   {
+    constexpr int XS = (OC * NCH * 64) / (SIN * 64 + NCH * 64);
+    constexpr int QR = 2 + XS;
+    auto xcost = [&](int e) { return lds + e * SIN * 64; };
+    auto xguide = [&](int e) { return lds + XS * SIN * 64 + e * NCH * 64; };
     const int ra = max(0, y0 - R), rb = min(H - 1, y0 + R);
-    for (int yy = ra; yy <= rb; yy += 2) {
-      const bool two = yy + 1 <= rb;
-      stage_cost(yy, 0);
-      if (two) stage_cost(yy + 1, 1);
+    for (int y00 = ra; y00 <= rb; y00 += QR) {
+      const int cnt = min(QR, rb - y00 + 1);
+      stage_cost(y00, 0);
+      if (cnt > 1) stage_cost(y00 + 1, 1);
+      for (int e = 0; e + 2 < cnt; ++e) stage_to(y00 + 2 + e, xcost(e), xguide(e));
       __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (box_wave) {
-        if (two)
+        if (cnt > 1)
           coef_vrow_lds<1, 1, CHECK, CPW, NCH, SIN, TIN>(vs, slot0, slot1, g40, launder(),
                                                        W, wv, lane);
         else
           coef_vrow_lds<1, 0, CHECK, CPW, NCH, SIN, TIN>(vs, slot0, slot1, g40, launder(),
                                                        W, wv, lane);
+        for (int e = 0; e + 2 < cnt; e += 2) {
+          const float4* gx = reinterpret_cast<const float4*>(xguide(e));
+          if (e + 3 < cnt)
+            coef_vrow_lds<1, 1, CHECK, CPW, NCH, SIN, TIN>(vs, xcost(e), xcost(e + 1), gx,
+                                                           launder(), W, wv, lane);
+          else
+            coef_vrow_lds<1, 0, CHECK, CPW, NCH, SIN, TIN>(vs, xcost(e), xcost(e), gx,
+                                                           launder(), W, wv, lane);
+        }
       }
       __syncthreads();
     }
