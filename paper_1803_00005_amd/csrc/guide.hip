@@ -131,7 +131,7 @@ __device__ __forceinline__ void add_moments(double (&vs)[KW], const double (&g)[
 }
 
 template <int R, int NG, int KW>
-__global__ __launch_bounds__((NG + NG * (NG + 1) / 2 + KW - 1) / KW * 64) void moments_cols_kernel(
+__global__ __launch_bounds__((NG + NG * (NG + 1) / 2 + KW - 1) / KW * 64) void moments_kernel(
     const double* __restrict__ g64, int H, int W, int band_h, int strips,
     double* __restrict__ S) {
   constexpr int K = NG + NG * (NG + 1) / 2;
@@ -597,14 +597,14 @@ hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
 }
 
 template <int R, int NG>
-static hipError_t moments_cols(const double* g64, int H, int W, int target, double* S,
+static hipError_t moments_n(const double* g64, int H, int W, int target, double* S,
                                hipStream_t s) {
   constexpr int K = NG + NG * (NG + 1) / 2;
   // one wave for up to 64 moments; above, eight waves of up to 27 moments
   constexpr int KW = K <= 64 ? K : (K + 7) / 8;
   constexpr int NWM = (K + KW - 1) / KW;
   StripGrid g = strip_grid(H, W, R, 1, target);
-  hipLaunchKernelGGL((moments_cols_kernel<R, NG, KW>),
+  hipLaunchKernelGGL((moments_kernel<R, NG, KW>),
                      dim3(static_cast<unsigned>(g.strips * g.bands)), dim3(NWM * 64), 0, s, g64,
                      H, W, g.band_h, g.strips, S);
   return hipGetLastError();
@@ -614,16 +614,16 @@ template <int R>
 static hipError_t moments_r(const double* g64, int n, int H, int W, int target, double* S,
                            hipStream_t s) {
   switch (n) {
-    case 1: return moments_cols<R, 1>(g64, H, W, target, S, s);
-    case 2: return moments_cols<R, 2>(g64, H, W, target, S, s);
-    case 3: return moments_cols<R, 3>(g64, H, W, target, S, s);
-    case 4: return moments_cols<R, 4>(g64, H, W, target, S, s);
-    case 5: return moments_cols<R, 5>(g64, H, W, target, S, s);
-    case 6: return moments_cols<R, 6>(g64, H, W, target, S, s);
-    case 7: return moments_cols<R, 7>(g64, H, W, target, S, s);
-    case 8: return moments_cols<R, 8>(g64, H, W, target, S, s);
-    case 9: return moments_cols<R, 9>(g64, H, W, target, S, s);
-    case 19: return moments_cols<R, 19>(g64, H, W, target, S, s);
+    case 1: return moments_n<R, 1>(g64, H, W, target, S, s);
+    case 2: return moments_n<R, 2>(g64, H, W, target, S, s);
+    case 3: return moments_n<R, 3>(g64, H, W, target, S, s);
+    case 4: return moments_n<R, 4>(g64, H, W, target, S, s);
+    case 5: return moments_n<R, 5>(g64, H, W, target, S, s);
+    case 6: return moments_n<R, 6>(g64, H, W, target, S, s);
+    case 7: return moments_n<R, 7>(g64, H, W, target, S, s);
+    case 8: return moments_n<R, 8>(g64, H, W, target, S, s);
+    case 9: return moments_n<R, 9>(g64, H, W, target, S, s);
+    case 19: return moments_n<R, 19>(g64, H, W, target, S, s);
     default: return hipErrorNotSupported;
   }
 }
