@@ -504,8 +504,28 @@ PAPER_TABLE2_MS = {250: {3: 3.9, 5: 10.7, 7: 39.9, 9: 110.2},
                    2000: {3: 4.3, 5: 11.2, 7: 42.7, 9: 121.8}}
 
 
-def secondary_gray(ctx, sizes=(250, 500, 1000, 2000), ns=(3, 5, 7, 9), reps=10):
+def sampled_error_ridge(w: synth.Workload, guide, cost, Z, k: int = 8, seed: int = 0):
+    """Max error of a one-label ridge-form Z (device) against the FP64 oracle at k
+    random pixels and two corners."""
+    from oracle import hgf_oracle as O
+    g = guide.cpu().numpy()
+    v = _DeviceCrop(cost)
+    rng = np.random.default_rng(seed)
+    pts = sorted({(0, 0), (w.height - 1, w.width - 1)} |
+                 {(int(rng.integers(0, w.height)), int(rng.integers(0, w.width)))
+                  for _ in range(k)})
+    Zo = O.filter_points(O.guidance(g, w.degree, w.basis), v, w.radius, w.eps, pts, mode="ridge")
+    vmax = max(float(np.abs(v[y, x]).max()) for (y, x) in pts)
+    idx = tuple(np.array(pts).T)
+    Zg = Z[idx].double().cpu().numpy()
+    rel = float(np.max(np.abs(Zg - Zo) / np.maximum(np.abs(Zo), vmax)))
+    return {"max_rel_vs_fp64_oracle": rel, "tolerance": 1e-4, "points": len(pts)}
+
+
+def secondary_gray(ctx, sizes=(250, 500, 1000, 2000), ns=(3, 5, 7, 9), reps=10, check=True):
     import torch
+
+    from paper_1803_00005_amd import hgf
     dev = torch.device("cuda", 0)
     rows = []
     for side in sizes:
@@ -514,8 +534,13 @@ def secondary_gray(ctx, sizes=(250, 500, 1000, 2000), ns=(3, 5, 7, 9), reps=10):
                                labels=1, radius=7, eps=0.05, degree=n, disparity="planar",
                                seed=9000 + side + n, guide_channels=1, basis="power")
             g, c = synth.make_workload_device(w, dev)
+            p = hgf.make_params(side, side, 1, radius=w.radius, eps=w.eps, degree=n,
+                                guide_channels=1, basis="power", reg="ridge")
+            ws = torch.empty(hgf.workspace_size(p), dtype=torch.uint8, device=dev)
+            Z = torch.empty((side, side, 1), dtype=torch.float32, device=dev)
             f = lambda: ctx.filter(g, c, radius=w.radius, eps=w.eps, degree=w.degree,
-                                   basis="power", reg="ridge", want_labels=False)
+                                   basis="power", reg="ridge", want_labels=False, out=Z,
+                                   workspace=ws)
             f()
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
@@ -525,9 +550,12 @@ def secondary_gray(ctx, sizes=(250, 500, 1000, 2000), ns=(3, 5, 7, 9), reps=10):
                 f()
             e1.record()
             torch.cuda.synchronize()
-            rows.append({"side": side, "n": n, "ms": e0.elapsed_time(e1) / reps,
-                         "paper_gtx960_ms": PAPER_TABLE2_MS[side][n]})
-            del g, c
+            row = {"side": side, "n": n, "ms": e0.elapsed_time(e1) / reps,
+                   "paper_gtx960_ms": PAPER_TABLE2_MS[side][n]}
+            if check and side == sizes[-1]:
+                row["error"] = sampled_error_ridge(w, g, c, Z)
+            rows.append(row)
+            del g, c, ws, Z
     say("gray sweep: " + ", ".join(f"{r['side']}/{r['n']}: {r['ms']:.3f} ms" for r in rows[-4:]))
     return {"form": "gray_power_ridge", "workload": "gray_power_r7_lambda0.05_L1",
             "note": "one slice (L = 1) per filter, ridge form of Eq. 6 with the power basis; the "
@@ -636,7 +664,7 @@ def main():
     if "inverse" in secondary:
         sec.append(secondary_inverse())
     if "gray" in secondary:
-        sec.append(secondary_gray(ctx))
+        sec.append(secondary_gray(ctx, check=not args.no_check))
     if "serve" in secondary:
         sec.append(secondary_serve(ctx, args.serve_requests, args.serve_pool, args.serve_rate,
                                    args.serve_slots, args.serve_arena_gb))

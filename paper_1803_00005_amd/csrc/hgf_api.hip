@@ -379,6 +379,30 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
                       const float* g32, const void* minv, float* wsbuf,
                       hipStream_t s) {
   const size_t esz = pl.bf16 ? 2 : 4;
+  if (pl.L == 1 && count == 1) {
+    // a one-label filter: lanes as pixels (the label-lane kernels would idle
+    // 63 lanes).  Only for filters of one label, so that a one-label chunk of
+    // a larger filter takes the same kernels as the whole filter.
+    SingleLaunch sa;
+    sa.cost = cost;
+    sa.cost_bf16 = pl.bf16;
+    sa.cost_ld = cost_ld;
+    sa.g32 = g32;
+    sa.minv = minv;
+    sa.ws = wsbuf;
+    sa.out = out;
+    sa.out_ld = out_ld;
+    sa.keys = keys;
+    sa.label = label_base;
+    sa.n = pl.n;
+    sa.H = pl.H;
+    sa.W = pl.W;
+    sa.R = pl.R;
+    sa.reg = pl.reg;
+    Stage st(ctx, 4, s);
+    HGF_TRY(launch_single(sa, s), "single-slice filter");
+    return HGF_OK;
+  }
   const int coef_target = tuned_target(ctx, kTuneCoef, pl);
   const int out_target = tuned_target(ctx, kTuneOut, pl);
   for (int l0 = 0; l0 < count; l0 += pl.chunks_per_launch * 64) {

@@ -125,6 +125,24 @@ hipError_t launch_out_n8(const OutLaunch& a, hipStream_t s);
 hipError_t launch_out_n9(const OutLaunch& a, hipStream_t s);
 hipError_t launch_out_n19(const OutLaunch& a, hipStream_t s);
 
+// a4 - a7 for a single label slice (L = 1) with lanes as pixels: separable
+// box sums over planar images in the workspace, which needs room for
+// 2 (n + 1) float32 images of P pixels.
+struct SingleLaunch {
+  const void* cost;     // [H][W][cost_ld], the label at offset 0
+  int cost_bf16;
+  int cost_ld;
+  const float* g32;     // planar [n+1][P], channel 0 = 1, padded
+  const void* minv;     // covariance records or ridge packed inverses
+  float* ws;            // >= 2 (n+1) P floats
+  float* out;           // [H][W][out_ld] or null
+  int out_ld;
+  unsigned long long* keys;  // [P] or null
+  int label;            // absolute label of the slice
+  int n, H, W, R, reg;
+};
+hipError_t launch_single(const SingleLaunch& a, hipStream_t s);
+
 // Fill `count` keys with ~0 (no hipMemsetAsync: safe under graph capture).
 hipError_t launch_key_fill(unsigned long long* keys, size_t count, hipStream_t s);
 // labels / best cost from keys; merge != 0 keeps the incoming (best, label)

@@ -93,6 +93,10 @@ CASES = [
     W("single_row", height=1, width=83, labels=5, radius=9, degree=2, seed=20),
     W("narrower_than_window", height=9, width=5, labels=4, radius=9, degree=1, seed=21),
     W("one_label", height=33, width=41, labels=1, radius=4, degree=2, seed=22),
+    W("one_label_n19_ragged", height=37, width=300, labels=1, radius=9, degree=3, eps=1e-3,
+      seed=24),
+    W("one_label_bf16", height=41, width=29, labels=1, radius=2, degree=2, cost_dtype="bf16",
+      seed=25),
     W("tall_n3_r7", height=140, width=20, labels=12, radius=7, degree=1, seed=23),
 ]
 
@@ -115,6 +119,10 @@ RIDGE_CASES = [
       eps=0.01, seed=33),
     W("ridge_n9_r9", height=48, width=66, degree=2, labels=20, radius=9, eps=0.05, seed=34),
     W("ridge_n19_r4", height=30, width=44, degree=3, labels=20, radius=4, eps=0.05, seed=35),
+    # one slice of a gray image under the power basis: the setting of Tables 1-2
+    W("ridge_gray_power_L1", height=70, width=300, guide_channels=1, basis="power", degree=5,
+      labels=1, radius=7, eps=0.05, seed=36),
+    W("ridge_n9_L1", height=40, width=90, degree=2, labels=1, radius=4, eps=0.05, seed=37),
 ]
 
 
