@@ -98,8 +98,8 @@ __device__ __forceinline__ void out_strip(const float* __restrict__ wsc,
                                           const float* __restrict__ g32, float* __restrict__ out,
                                           int out_ld, unsigned long long* __restrict__ keys,
                                           int label_base, int H, int W, int xs, int x_out0,
-                                          int y0, int y1, int lab, bool lab_ok, int wv, int lane,
-                                          double* __restrict__ part) {
+                                          int y0, int y1, bool up, int lab, bool lab_ok, int wv,
+                                          int lane, double* __restrict__ part) {
   constexpr int NCH = NG + 1;
   constexpr int NW = (NCH + CPW - 1) / CPW;
   constexpr int SOUT = SIN - 2 * R;
@@ -121,22 +121,32 @@ __device__ __forceinline__ void out_strip(const float* __restrict__ wsc,
     return __builtin_amdgcn_readfirstlane(xsl);
   };
 
-  // initial window of the band: rows y0 - R .. y0 + R (two at a time when paired)
+  // Even bands run upward from their last row, odd bands downward from their
+  // first: the two blocks of a band boundary then start on nearly the same
+  // 2R + 1 rows at the same time (and end on the same rows at their other
+  // boundaries), so the start-up rows are shared through L2 rather than read
+  // twice from HBM.
+  const int ystart = up ? y1 - 1 : y0;
+  // initial window: rows ystart - R .. ystart + R (two at a time when paired)
   {
-    const int ra = max(0, y0 - R), rb = min(H - 1, y0 + R);
+    const int ra = max(0, ystart - R), rb = min(H - 1, ystart + R);
     int yy = ra;
     for (; PAIR && yy + 1 <= rb; yy += 2)
       out_vrow<1, 1, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, yy, yy + 1, launder(), W, wv, lane);
     for (; yy <= rb; ++yy) out_vrow<1, 0, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, yy, 0, launder(), W, wv, lane);
   }
-  for (int y = y0; y < y1; ++y) {
-    if (y > y0) {
-      const bool a = y + R < H, s = y - R - 1 >= 0;
+  const int dir = up ? -1 : 1;
+  for (int t = 0; t < y1 - y0; ++t) {
+    const int y = ystart + dir * t;
+    if (t > 0) {
+      // the row entering the window and the row leaving it
+      const int ye = y + dir * R, yl = y - dir * (R + 1);
+      const bool a = ye >= 0 && ye < H, s = yl >= 0 && yl < H;
       if (PAIR && a && s) {
-        out_vrow<1, -1, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, y + R, y - R - 1, launder(), W, wv, lane);
+        out_vrow<1, -1, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, ye, yl, launder(), W, wv, lane);
       } else {
-        if (a) out_vrow<1, 0, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, y + R, 0, launder(), W, wv, lane);
-        if (s) out_vrow<0, -1, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, 0, y - R - 1, launder(), W, wv, lane);
+        if (a) out_vrow<1, 0, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, ye, 0, launder(), W, wv, lane);
+        if (s) out_vrow<0, -1, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, 0, yl, launder(), W, wv, lane);
       }
     }
     double hs[CPW];
@@ -241,10 +251,10 @@ __global__ __launch_bounds__(640) void out_kernel(
   const float* __restrict__ wsc = ws + static_cast<size_t>(chunk) * P * NCH * 64;
   if (xs >= 0 && xs + SIN <= W)
     out_strip<R, CPW, NG, SIN, GRP, PAIR, false>(wsc, g32, out, out_ld, keys, label_base, H, W, xs,
-                                           x_out0, y0, y1, lab, lab_ok, wv, lane, part);
+                                           x_out0, y0, y1, (band & 1) == 0, lab, lab_ok, wv, lane, part);
   else
     out_strip<R, CPW, NG, SIN, GRP, PAIR, true>(wsc, g32, out, out_ld, keys, label_base, H, W, xs,
-                                          x_out0, y0, y1, lab, lab_ok, wv, lane, part);
+                                          x_out0, y0, y1, (band & 1) == 0, lab, lab_ok, wv, lane, part);
 }
 
 template <int R, int NG>
