@@ -10,9 +10,10 @@
 // wave forms the partial dot product of its channels with the (wave-uniform)
 // guidance at every output column; the partials meet in LDS and are summed in
 // a fixed order, so Z does not depend on scheduling.  The winner-takes-all
-// key (ordered cost bits << 32 | label) is reduced across the 64 lanes with
-// shuffles and merged into a per-pixel 64-bit minimum; the minimum of keys
-// is order independent, so label chunks may run concurrently.
+// key (ordered cost bits << 32 | label) of the 64 lanes is formed from the
+// lanes' minimum (DPP row minima, then the four row values) and the lowest
+// lane holding it, and merged into a per-pixel 64-bit minimum; the minimum
+// of keys is order independent, so label chunks may run concurrently.
 //
 // With one channel per wave a row step loads the entering and the leaving row
 // of the vertical window together, a group of columns at a time, so each
@@ -235,12 +236,24 @@ __global__ __launch_bounds__(640) void out_kernel(
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // work item of this block; integer division runs on the vector ALU, so the
   // results are moved back to scalar registers explicitly
+  // logical order: label chunk fastest, then the two bands of a band pair
+  // (which share their start-up rows), then strip, then band pair; a last
+  // unpaired band comes after all pairs.  Each XCD gets a contiguous range.
   int bid = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
   const int chunks = __builtin_amdgcn_readfirstlane(static_cast<int>(gridDim.x) / (strips * bands));
+  const int paired = (bands / 2) * 2;
   const int chunk = __builtin_amdgcn_readfirstlane(bid % chunks);
-  bid = __builtin_amdgcn_readfirstlane(bid / chunks);
-  const int strip = __builtin_amdgcn_readfirstlane(bid % strips);
-  const int band = __builtin_amdgcn_readfirstlane(bid / strips);
+  int strip, band;
+  if (bid < strips * paired * chunks) {
+    bid = __builtin_amdgcn_readfirstlane(bid / chunks);
+    const int par = bid & 1;
+    bid >>= 1;
+    strip = __builtin_amdgcn_readfirstlane(bid % strips);
+    band = __builtin_amdgcn_readfirstlane((bid / strips) * 2 + par);
+  } else {
+    strip = __builtin_amdgcn_readfirstlane((bid - strips * paired * chunks) / chunks);
+    band = paired;
+  }
   const int x_out0 = strip * SOUT;
   const int xs = x_out0 - R;
   const int y0 = band * band_h;
