@@ -375,7 +375,8 @@ hgf_status run_guide(hgf_context* ctx, const Plan& pl, const float* guide, void*
 }
 
 hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int cost_ld, float* out,
-                      int out_ld, unsigned long long* keys, int label_base, int count,
+                      int out_ld, unsigned long long* keys, int32_t* labels, int label_base,
+                      int count,
                       const float* g32, const void* minv, float* wsbuf,
                       hipStream_t s) {
   const size_t esz = pl.bf16 ? 2 : 4;
@@ -393,6 +394,7 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
     sa.out = out;
     sa.out_ld = out_ld;
     sa.keys = keys;
+    sa.labels = labels;
     sa.label = label_base;
     sa.n = pl.n;
     sa.H = pl.H;
@@ -432,6 +434,7 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
     oa.out = out != nullptr ? out + l0 : nullptr;
     oa.out_ld = out_ld;
     oa.keys = keys;
+    oa.labels = labels;
     oa.label_base = label_base + l0;
     oa.n = pl.n;
     oa.H = pl.H;
@@ -453,12 +456,17 @@ hgf_status run_filter(hgf_context* ctx, const Plan& pl, const float* guide, cons
                       hipStream_t s) {
   hgf_status st = run_guide(ctx, pl, guide, ws, s);
   if (st != HGF_OK) return st;
-  unsigned long long* keys = labels != nullptr ? at<unsigned long long>(ws, pl.off_keys) : nullptr;
+  // With every label in one chunk of one launch the output kernel writes the
+  // final labels itself; otherwise the chunks merge per-pixel keys.
+  const bool direct = labels != nullptr && pl.L <= 64;
+  unsigned long long* keys =
+      (labels != nullptr && !direct) ? at<unsigned long long>(ws, pl.off_keys) : nullptr;
   if (keys != nullptr) {
     Stage sk(ctx, 6, s);
     HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
   }
-  st = run_labels(ctx, pl, cost, cost_ld, out, out_ld, keys, 0, pl.L, pl.g32(ws),
+  st = run_labels(ctx, pl, cost, cost_ld, out, out_ld, keys, direct ? labels : nullptr, 0, pl.L,
+                  pl.g32(ws),
                   at<char>(ws, pl.off_minv), at<float>(ws, pl.off_x),
                   s);
   if (st != HGF_OK) return st;
@@ -607,7 +615,8 @@ hgf_status hgf_guide_filter(hgf_context* ctx, hgf_guide* g, const void* cost_chu
     Stage sk(ctx, 6, s);
     HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
   }
-  const hgf_status st = run_labels(ctx, pl, cost_chunk, ldv, out_chunk, ldv, keys, label_begin,
+  const hgf_status st = run_labels(ctx, pl, cost_chunk, ldv, out_chunk, ldv, keys, nullptr,
+                                   label_begin,
                                    label_count, pl.g32(base),
                                    at<char>(base, pl.off_minv), at<float>(base, pl.off_x), s);
   if (st != HGF_OK) return st;

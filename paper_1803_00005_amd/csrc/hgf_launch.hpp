@@ -107,6 +107,7 @@ struct OutLaunch {
   float* out;           // [H][W][out_ld] or null
   int out_ld;
   unsigned long long* keys;  // [P] or null
+  int32_t* labels;      // [P] or null: final labels, when every label is in this one chunk
   int label_base;       // absolute label of lane 0 of chunk 0
   int n, H, W, R;
   int label_count;
@@ -138,6 +139,7 @@ struct SingleLaunch {
   float* out;           // [H][W][out_ld] or null
   int out_ld;
   unsigned long long* keys;  // [P] or null
+  int32_t* labels;      // [P] or null: final labels (the slice is the only label)
   int label;            // absolute label of the slice
   int n, H, W, R, reg;
 };

@@ -13,7 +13,8 @@
 // key (ordered cost bits << 32 | label) of the 64 lanes is formed from the
 // lanes' minimum (DPP row minima, then the four row values) and the lowest
 // lane holding it, and merged into a per-pixel 64-bit minimum; the minimum
-// of keys is order independent, so label chunks may run concurrently.
+// of keys is order independent, so label chunks may run concurrently.  When
+// all labels are in one chunk the label itself is written instead.
 //
 // With one channel per wave a row step loads the entering and the leaving row
 // of the vertical window together, a group of columns at a time, so each
@@ -98,7 +99,7 @@ template <int R, int CPW, int NG, int SIN, int GRP, bool PAIR, bool CHECK>
 __device__ __forceinline__ void out_strip(const float* __restrict__ wsc,
                                           const float* __restrict__ g32, float* __restrict__ out,
                                           int out_ld, unsigned long long* __restrict__ keys,
-                                          int label_base, int H, int W, int xs, int x_out0,
+                                          int32_t* __restrict__ labels, int label_base, int H, int W, int xs, int x_out0,
                                           int y0, int y1, bool up, int lab, bool lab_ok, int wv,
                                           int lane, double* __restrict__ part) {
   constexpr int NCH = NG + 1;
@@ -202,7 +203,7 @@ __device__ __forceinline__ void out_strip(const float* __restrict__ wsc,
           z /= static_cast<double>(window_count(x, y, W, H, R));
           const float zf = static_cast<float>(z);
           if (out != nullptr && lab_ok) out[p * out_ld + lab] = zf;
-          if (keys != nullptr) {
+          if (keys != nullptr || labels != nullptr) {
             // lowest ordered cost of the 64 labels, then the lowest lane
             // holding it (labels increase with the lane)
             const uint32_t u = lab_ok ? ordered_bits(zf) : 0xffffffffu;
@@ -212,7 +213,13 @@ __device__ __forceinline__ void out_strip(const float* __restrict__ wsc,
             const uint32_t hi = __builtin_amdgcn_readfirstlane(m);
             const uint32_t lo = __builtin_amdgcn_readfirstlane(label_base + (lab - lane) + first);
             const unsigned long long key = (static_cast<unsigned long long>(hi) << 32) | lo;
-            if (lane == 0) atomicMin(&keys[p], key);
+            if (lane == 0) {
+              // all labels in this one chunk: the label is final
+              if (labels != nullptr)
+                labels[p] = static_cast<int32_t>(lo);
+              else
+                atomicMin(&keys[p], key);
+            }
           }
         }
       }
@@ -224,7 +231,8 @@ __device__ __forceinline__ void out_strip(const float* __restrict__ wsc,
 template <int R, int CPW, int NG, int SIN, int GRP, bool PAIR>
 __global__ __launch_bounds__(640) void out_kernel(
     const float* __restrict__ ws, const float* __restrict__ g32, float* __restrict__ out,
-    int out_ld, unsigned long long* __restrict__ keys, int label_base, int H, int W,
+    int out_ld, unsigned long long* __restrict__ keys, int32_t* __restrict__ labels,
+    int label_base, int H, int W,
     int label_count, int band_h, int strips, int bands) {
   constexpr int NCH = NG + 1;
   constexpr int NW = (NCH + CPW - 1) / CPW;
@@ -263,10 +271,12 @@ __global__ __launch_bounds__(640) void out_kernel(
   const size_t P = static_cast<size_t>(H) * W;
   const float* __restrict__ wsc = ws + static_cast<size_t>(chunk) * P * NCH * 64;
   if (xs >= 0 && xs + SIN <= W)
-    out_strip<R, CPW, NG, SIN, GRP, PAIR, false>(wsc, g32, out, out_ld, keys, label_base, H, W, xs,
+    out_strip<R, CPW, NG, SIN, GRP, PAIR, false>(wsc, g32, out, out_ld, keys, labels, label_base, H, W,
+                                                 xs,
                                            x_out0, y0, y1, (band & 1) == 0, lab, lab_ok, wv, lane, part);
   else
-    out_strip<R, CPW, NG, SIN, GRP, PAIR, true>(wsc, g32, out, out_ld, keys, label_base, H, W, xs,
+    out_strip<R, CPW, NG, SIN, GRP, PAIR, true>(wsc, g32, out, out_ld, keys, labels, label_base, H, W,
+                                                 xs,
                                           x_out0, y0, y1, (band & 1) == 0, lab, lab_ok, wv, lane, part);
 }
 
@@ -283,7 +293,7 @@ hipError_t out_launch_t(const OutLaunch& a, hipStream_t s) {
   const StripGrid& g = a.grid;
   const unsigned blocks = static_cast<unsigned>(g.strips * g.bands * g.chunks);
   hipLaunchKernelGGL((out_kernel<R, CPW, NG, SIN, GRP, PAIR>), dim3(blocks), dim3(NW * 64), 0, s, a.ws,
-                     a.g32, a.out, a.out_ld, a.keys, a.label_base, a.H, a.W, a.label_count,
+                     a.g32, a.out, a.out_ld, a.keys, a.labels, a.label_base, a.H, a.W, a.label_count,
                      g.band_h, g.strips, g.bands);
   return hipGetLastError();
 }

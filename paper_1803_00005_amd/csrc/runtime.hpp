@@ -138,7 +138,8 @@ int tuned_target(hgf_context* ctx, int kernel, const Plan& pl);
 hgf_status run_guide(hgf_context* ctx, const Plan& pl, const float* guide, void* ws,
                      hipStream_t s);
 hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int cost_ld, float* out,
-                      int out_ld, unsigned long long* keys, int label_base, int count,
+                      int out_ld, unsigned long long* keys, int32_t* labels, int label_base,
+                      int count,
                       const float* g32, const void* minv, float* wsbuf,
                       hipStream_t s);
 // Whole image: guide + labels + winner-takes-all into `labels`.

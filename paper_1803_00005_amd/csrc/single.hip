@@ -10,7 +10,7 @@
 //      Eq. 6)
 //   3. vertical window sums of the n + 1 coefficient images
 //   4. horizontal window sums (float64) and Z = sum_ch B(w_ch) G_ch / N (Eq. 11);
-//      the winner-takes-all key of the single label.
+//      the label (the only one) or its winner-takes-all key.
 // The same arithmetic as the label-lane path, in another summation order.
 #include "hgf_launch.hpp"
 
@@ -88,7 +88,6 @@ __global__ __launch_bounds__(256) void single_solve_kernel(const float* __restri
                                                            int W, int R) {
   constexpr int NCH = NG + 1;
   constexpr int D = RIDGE ? NCH : NG;
-  constexpr int PD = D * (D + 1) / 2;
   constexpr int RW = minv_stride(RIDGE, NG);
   const size_t P = static_cast<size_t>(H) * W;
   const size_t p = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
@@ -139,20 +138,20 @@ __global__ __launch_bounds__(256) void single_solve_kernel(const float* __restri
         if (j != i) w[j] = fma(m, T[i], w[j]);
       }
     }
-    (void)PD;
 #pragma unroll
     for (int i = 0; i < D; ++i) coef[i * P + p] = static_cast<float>(w[i]);
   }
 }
 
 // Horizontal sums of the vertically summed coefficients, the output and the
-// winner-takes-all key of the one label.
+// label (or its winner-takes-all key, when the caller merges label chunks).
 template <int NG>
 __global__ __launch_bounds__(256) void single_out_kernel(const float* __restrict__ vbox,
                                                          const float* __restrict__ g32,
                                                          float* __restrict__ out, int out_ld,
                                                          unsigned long long* __restrict__ keys,
-                                                         int label, int H, int W, int R) {
+                                                         int32_t* __restrict__ labels, int label,
+                                                         int H, int W, int R) {
   constexpr int NCH = NG + 1;
   const size_t P = static_cast<size_t>(H) * W;
   const size_t p = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
@@ -167,7 +166,10 @@ __global__ __launch_bounds__(256) void single_out_kernel(const float* __restrict
   z /= static_cast<double>(window_count(x, y, W, H, R));
   const float zf = static_cast<float>(z);
   if (out != nullptr) out[p * out_ld] = zf;
-  if (keys != nullptr) atomicMin(&keys[p], wta_key(zf, label));
+  if (labels != nullptr)
+    labels[p] = label;
+  else if (keys != nullptr)
+    atomicMin(&keys[p], wta_key(zf, label));
 }
 
 template <int NG, typename TIN>
@@ -190,7 +192,7 @@ hipError_t single_launch_t(const SingleLaunch& a, hipStream_t s) {
   hipLaunchKernelGGL((single_vbox_kernel<NCH, 0, float>), vgrid, dim3(256), 0, s, nullptr,
                      static_cast<const float*>(nullptr), 0, c, v, a.H, a.W, a.R);
   hipLaunchKernelGGL((single_out_kernel<NG>), dim3(pgrid), dim3(256), 0, s, v, a.g32, a.out,
-                     a.out_ld, a.keys, a.label, a.H, a.W, a.R);
+                     a.out_ld, a.keys, a.labels, a.label, a.H, a.W, a.R);
   return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ hgf_status time_path(hgf_context* ctx, const Plan& pl, const float* guide, const
       st = fail(HGF_E_DEVICE, "key_fill");
       break;
     }
-    st = run_labels(ctx, pl, cost, cost_ld, out, out_ld, keys, 0, pl.L, pl.g32(ws),
+    st = run_labels(ctx, pl, cost, cost_ld, out, out_ld, keys, nullptr, 0, pl.L, pl.g32(ws),
                     at<char>(ws, pl.off_minv), at<float>(ws, pl.off_x),
                     s);
   }
