@@ -22,9 +22,11 @@ __device__ __forceinline__ double monomial(const MonoTable& t, int k, const floa
 }
 
 // ---------------------------------------------------------------------------
-// a1: channel means (deterministic two-stage reduction) and the synthesized
-// guidance.  Each block reduces a fixed pixel subset in a fixed order, so the
-// result does not depend on scheduling.
+// a1: the channel shifts and the synthesized guidance.  The covariance form
+// is invariant to a constant shift of each guidance channel, so any constant
+// is exact; the shift only centres the values for float32 conditioning.  It
+// is the channel mean over a fixed grid of at most 64 x 64 pixels, reduced by
+// one block in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
 // Sum over the 64 lanes of a wave by a fixed butterfly (deterministic).
 __device__ __forceinline__ double wave_sum(double v) {
@@ -33,50 +35,47 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(256) void guide_mean_partial_kernel(
-    const float* __restrict__ I, int P, MonoTable t, double* __restrict__ partial) {
-  __shared__ double red[4][kMaxD];
-  double acc[kMaxD];
-#pragma unroll
-  for (int k = 0; k < kMaxD; ++k) acc[k] = 0.0;
-  for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256) {
-    float iv[4] = {0.f, 0.f, 0.f, 0.f};
+constexpr int kShiftGrid = kShiftRows;  // sample grid: at most 64 x 64 pixels
+
+// One wave per row of the sample grid (one sample per lane), then one wave
+// for the rows' partial sums.
+__global__ __launch_bounds__(64) void guide_shift_partial_kernel(const float* __restrict__ I,
+                                                                 int H, int W, MonoTable t,
+                                                                 double* __restrict__ partial) {
+  const int sy = (H + kShiftGrid - 1) / kShiftGrid, sx = (W + kShiftGrid - 1) / kShiftGrid;
+  const int nx = (W + sx - 1) / sx;
+  const size_t P = static_cast<size_t>(H) * W;
+  const int lane = threadIdx.x;
+  const int y = static_cast<int>(blockIdx.x) * sy;
+  float iv[4] = {0.f, 0.f, 0.f, 0.f};
+  if (lane < nx) {
+    const size_t p = static_cast<size_t>(y) * W + lane * sx;
     for (int c = 0; c < t.m; ++c) iv[c] = I[static_cast<size_t>(c) * P + p];
-#pragma unroll
-    for (int k = 0; k < kMaxD; ++k)
-      if (k < t.n) acc[k] += monomial(t, k, iv);
   }
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < kMaxD; ++k) {
     if (k < t.n) {
-      const double v = wave_sum(acc[k]);
-      if (lane == 0) red[wv][k] = v;
+      const double v = wave_sum(lane < nx ? monomial(t, k, iv) : 0.0);
+      if (lane == 0) partial[blockIdx.x * kMaxD + k] = v;
     }
   }
-  __syncthreads();
-  const int k = threadIdx.x;
-  if (k < t.n) partial[blockIdx.x * kMaxD + k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
 }
 
-// One block per channel: the kMeanBlocks partial sums in a fixed order.
-__global__ __launch_bounds__(256) void guide_mean_final_kernel(
-    const double* __restrict__ partial, int nblocks, int P, int centre,
-    double* __restrict__ shift) {
-  __shared__ double red[4];
-  const int k = blockIdx.x;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += 256) v += partial[b * kMaxD + k];
-  v = wave_sum(v);
-  if (lane == 0) red[wv] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double tot = ((red[0] + red[1]) + red[2]) + red[3];
-    shift[k] = centre ? tot / static_cast<double>(P) : 0.0;
-  }
+__global__ __launch_bounds__(64) void guide_shift_final_kernel(const double* __restrict__ partial,
+                                                               int H, int W, int n, int centre,
+                                                               double* __restrict__ shift) {
+  const int sy = (H + kShiftGrid - 1) / kShiftGrid, sx = (W + kShiftGrid - 1) / kShiftGrid;
+  const int ny = (H + sy - 1) / sy, nx = (W + sx - 1) / sx;
+  const int k = threadIdx.x;
+  if (k >= n) return;
+  // all row loads issued together, then summed in row order
+  double v[kShiftRows];
+#pragma unroll
+  for (int r = 0; r < kShiftRows; ++r) v[r] = r < ny ? partial[r * kMaxD + k] : 0.0;
+  double tot = 0.0;
+#pragma unroll
+  for (int r = 0; r < kShiftRows; ++r) tot += v[r];
+  shift[k] = centre ? tot / static_cast<double>(ny * nx) : 0.0;
 }
 
 // g32 holds n + 1 planar channels [n+1][P], channel 0 being the constant
@@ -577,13 +576,13 @@ __global__ __launch_bounds__(64) void spd_inverse_kernel(const double* __restric
 
 }  // namespace
 
-hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t,
-                             double* partial, double* shift, bool centre, hipStream_t s) {
-  const int P = H * W;
-  hipLaunchKernelGGL(guide_mean_partial_kernel, dim3(kMeanBlocks), dim3(256), 0, s, I, P, t,
-                     partial);
-  hipLaunchKernelGGL(guide_mean_final_kernel, dim3(t.n), dim3(256), 0, s, partial, kMeanBlocks,
-                     P, centre ? 1 : 0, shift);
+hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t, double* partial,
+                             double* shift, bool centre, hipStream_t s) {
+  const int sy = (H + kShiftGrid - 1) / kShiftGrid;
+  const int ny = (H + sy - 1) / sy;
+  hipLaunchKernelGGL(guide_shift_partial_kernel, dim3(ny), dim3(64), 0, s, I, H, W, t, partial);
+  hipLaunchKernelGGL(guide_shift_final_kernel, dim3(1), dim3(64), 0, s, partial, H, W, t.n,
+                     centre ? 1 : 0, shift);
   return hipGetLastError();
 }
 

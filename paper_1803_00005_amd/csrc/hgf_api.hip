@@ -200,7 +200,7 @@ Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
       std::max<size_t>(1, std::min<size_t>(chunks_total, kWsCapBytes / pl.ws_chunk_bytes)));
   size_t off = 0;
   pl.off_partial = off;
-  off = align_up(off + sizeof(double) * kMeanBlocks * kMaxD);
+  off = align_up(off + sizeof(double) * kShiftRows * kMaxD);
   pl.off_shift = off;
   off = align_up(off + sizeof(double) * kMaxD);
   pl.off_g64 = off;

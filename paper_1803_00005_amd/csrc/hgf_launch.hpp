@@ -8,9 +8,6 @@
 
 namespace hgf {
 
-// Blocks of the deterministic two-stage reduction of the guidance means.
-constexpr int kMeanBlocks = 256;
-
 // Per-launch geometry of a strip kernel: strips of (64 - 2R) output columns,
 // bands of band_h output rows, label chunks of 64 lanes.
 struct StripGrid {
@@ -37,12 +34,13 @@ bool radius_supported(int R);
 // (n, R, reg) has compiled coefficient / output / inverse kernels.
 bool config_supported(int n, int R, int reg);
 
-// a1 + shift: guidance means (covariance form: each channel is shifted by its
-// image mean, an exact reformulation since the window covariance does not
-// see a constant offset; ridge form: no shift).
-hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t,
-                             double* partial, double* shift, bool centre,
-                             hipStream_t s);
+// a1 + shift: guidance channel shifts (covariance form: each channel's mean
+// over a fixed grid of at most 64 x 64 pixels, an exact reformulation since
+// the window covariance does not see a constant offset; ridge form: 0).
+hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t, double* partial,
+                             double* shift, bool centre, hipStream_t s);
+// Rows of the shift sample grid (the partial sums need kShiftRows x kMaxD doubles).
+constexpr int kShiftRows = 64;
 // a1: synthesized (shifted) guidance: float64 [P][n] and planar float32
 // [n+1][P] with the constant channel G_0 = 1 first (g32 points at channel 0;
 // the allocation has kGPad floats before and after).
