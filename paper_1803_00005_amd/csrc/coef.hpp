@@ -10,17 +10,19 @@
 // images [b, a_1..a_n] go to a float32 workspace [chunk][P][n+1][64].
 //
 // Mapping (gfx950, wave64): the 64 lanes of a wave are 64 labels of one
-// pixel.  Everything per-pixel (M_p, mu_p, G(p), N_p) is wave-uniform and is
-// read with scalar loads into SGPRs, so the n x n times n x 64 product runs
-// as plain VALU FMAs with one scalar operand and no operand traffic.
-// A workgroup owns a strip of SIN state columns (SIN - 2R output columns) over
-// a band of rows.  Its waves split the n + 1 product channels: each wave keeps
-// float32 vertical running sums of its channels for all state columns in
-// registers (add the row entering the window, subtract the row leaving it)
-// and forms the horizontal window sums in registers with float64 running
-// sums, so the only shared-memory traffic is one transpose of the finished
-// window sums T, U of a row before the solves.  Bands restart the vertical
-// sums, which bounds float32 drift to band_h + 2R additions.
+// pixel.  Everything per-pixel (M_p, mu_p, G(p), N_p) is wave-uniform: M_p and
+// mu_p come from 16-byte broadcast reads of LDS, G(p) from broadcast reads of
+// the staged guidance, so the n x n times n x 64 product runs as plain VALU
+// FMAs.  A workgroup owns a strip of SIN state columns (SIN - 2R output
+// columns) over a band of rows.  Its waves split the n + 1 product channels:
+// each wave keeps float32 vertical running sums of its channels for all state
+// columns in registers (add the row entering the window, subtract the row
+// leaving it) and forms the horizontal window sums in registers with float64
+// running sums; the window sums T, U of a row are transposed through LDS
+// before the solves, which all waves of the block share.  The cost rows, the
+// guidance rows and the solve records reach LDS by direct-to-LDS loads issued
+// ahead of their use.  Bands restart the vertical sums, which bounds float32
+// drift to band_h + 2R additions.
 //
 // Strips inside the image take a path without column bounds handling; the two
 // border strips clamp their addresses and weight out-of-image columns by zero.
@@ -55,45 +57,6 @@ constexpr int coef_column_chunk() {
   if (oc < 1) oc = 1;
   const int ncb = (SOUT + oc - 1) / oc;
   return (SOUT + ncb - 1) / ncb;  // balanced chunks
-}
-
-// One vertical window update of every state column: SIGN (+1 or -1) times
-// the products G_ch * Y of row yy.
-template <int SIGN, bool CHECK, int CPW, int NCH, int SIN, typename TIN>
-__device__ __forceinline__ void coef_vrow(float (&vs)[CPW][SIN], const TIN* __restrict__ cost,
-                                          int cost_ld, const float* __restrict__ g32, size_t P,
-                                          int yy, int xsl, int W, int labc, int wv) {
-  const __amdgpu_buffer_rsrc_t crow = raw_rsrc(cost + static_cast<size_t>(yy) * W * cost_ld);
-  const int voff = labc * static_cast<int>(sizeof(TIN));
-  const int colb = cost_ld * static_cast<int>(sizeof(TIN));
-  const float* __restrict__ grow = g32 + static_cast<size_t>(yy) * W + xsl;
-#pragma unroll
-  for (int c0 = 0; c0 < SIN; c0 += kGrp) {
-    float yv[kGrp];
-#pragma unroll
-    for (int c = 0; c < kGrp; ++c) {
-      if (c0 + c < SIN) {
-        const int xr = xsl + c0 + c;
-        const int xc = CHECK ? min(max(xr, 0), W - 1) : xr;
-        yv[c] = buf_load_cost<TIN>(crow, voff, xc * colb);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < CPW; ++k) {
-      const int ch = wv * CPW + k;
-      const int chc = (NCH % CPW == 0) ? ch : min(ch, NCH - 1);
-      const float* __restrict__ gp = grow + static_cast<size_t>(chc) * P + c0;
-#pragma unroll
-      for (int c = 0; c < kGrp; ++c) {
-        if (c0 + c < SIN) {
-          const int xr = xsl + c0 + c;
-          const bool ok = ((NCH % CPW == 0) || ch < NCH) && (!CHECK || (xr >= 0 && xr < W));
-          const float g = ldu(gp, c);
-          vs[k][c0 + c] = fmaf(ok ? (SIGN > 0 ? g : -g) : 0.f, yv[c], vs[k][c0 + c]);
-        }
-      }
-    }
-  }
 }
 
 // Cost rows pass through LDS: a slot holds the SIN state columns of one row,

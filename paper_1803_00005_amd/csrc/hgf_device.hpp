@@ -16,20 +16,18 @@ constexpr int kMaxD = 20;
 // State columns per strip in the strip kernels: one wavefront-width of columns.
 constexpr int kStrip = 64;
 
-// Columns whose loads a strip kernel issues together before using them.
-constexpr int kGrp = 16;
-
 // Floats of padding before and after the planar float32 guidance [n+1][P]:
-// a strip reads 16 consecutive columns of a row with one scalar load, and the
-// columns of a group that fall outside the image (at most 31 on either side)
-// read padding or a neighbouring row; their weight is selected to 0.
+// the strip kernels read a row of a strip's columns as one block (64 columns
+// from the strip origin, which lies at most R columns before the image), so
+// columns outside the image read padding or a neighbouring row; their weight
+// is selected to 0.
 constexpr int kGPad = 64;
 
 // Read-only loads through the constant address space.  When the address is
 // wave-uniform the compiler emits scalar (SMEM) loads into SGPRs, so
-// per-pixel data shared by the 64 label lanes (the inverse M_p, the window
-// mean, the guidance value) costs no vector load and enters the VALU as a
-// scalar operand.
+// per-pixel data shared by the 64 label lanes (the guidance values of the
+// output kernel) costs no vector load and enters the VALU as a scalar
+// operand.
 template <typename T>
 __device__ __forceinline__ T ldu(const T* p, size_t i) {
   typedef const __attribute__((address_space(4))) T* const_ptr;
@@ -73,31 +71,6 @@ __device__ __forceinline__ float load_cost<uint16_t>(const uint16_t* p, size_t i
   return bf16_to_float(p[i]);
 }
 
-// Raw buffer resource over `base` (gfx9 descriptor word 3: 32-bit data
-// format, no swizzle; the record limit is not used for range checks here, the
-// kernels form in-range offsets only).  A buffer load takes a wave-uniform
-// byte offset in a scalar register and a per-lane byte offset in a vector
-// register, so addressing a column costs scalar instructions only.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, 0x00020000);
-}
-
-__device__ __forceinline__ float buf_load_f32(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-
-template <typename T>
-__device__ __forceinline__ float buf_load_cost(__amdgpu_buffer_rsrc_t r, int voff, int soff);
-template <>
-__device__ __forceinline__ float buf_load_cost<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return buf_load_f32(r, voff, soff);
-}
-template <>
-__device__ __forceinline__ float buf_load_cost<uint16_t>(__amdgpu_buffer_rsrc_t r, int voff,
-                                                         int soff) {
-  return bf16_to_float(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
-}
-
 // Order-preserving map of a float to uint32 (NaN canonicalised to +qNaN, which
 // sorts above +inf): a < b  <=>  ordered(a) < ordered(b).
 __device__ __forceinline__ uint32_t ordered_bits(float f) {
@@ -137,15 +110,6 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   const uint32_t c = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 32));
   const uint32_t d = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), 48));
   return min(min(a, b), min(c, d));
-}
-
-__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const unsigned long long o = __shfl_xor(v, off, 64);
-    v = o < v ? o : v;
-  }
-  return v;
 }
 
 }  // namespace hgf

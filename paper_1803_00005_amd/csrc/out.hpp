@@ -26,7 +26,6 @@
 #include "hgf_launch.hpp"
 
 namespace hgf {
-constexpr int kOutMaxWaves = 10;
 // LDS for the per-wave partial dot products (float64) of one column chunk
 constexpr int kOutPartBytes = 120 * 1024;
 
