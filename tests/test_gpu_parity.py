@@ -222,6 +222,27 @@ def test_two_phase_chunks_equal_plain_path(ctx):
     np.testing.assert_array_equal(best.cpu().numpy(), Zp.astype(np.float32).min(axis=2))
 
 
+def test_two_phase_one_label_equals_plain_path(ctx):
+    """A one-label filter through the two-phase interface (per-pixel keys merged
+    by the caller's running minimum) equals the plain call (labels written
+    directly) bit for bit."""
+    w = [c for c in CASES if c.name == "one_label"][0]
+    say(f"two-phase one-label vs plain: {w.name}")
+    guide, cost = synth.make_workload(w)
+    Zp, labp = gpu_filter(ctx, guide, cost, w)
+    g = hgf.Guide(ctx, to_dev(guide), labels=1, radius=w.radius, eps=w.eps, degree=w.degree)
+    H, Wd, _ = cost.shape
+    best = torch.empty((H, Wd), dtype=torch.float32, device=dev())
+    lab = torch.empty((H, Wd), dtype=torch.int32, device=dev())
+    out = torch.empty((H, Wd, 1), dtype=torch.float32, device=dev())
+    g.filter(to_dev(cost), 0, out=out, best=best, labels=lab)
+    torch.cuda.synchronize()
+    g.close()
+    np.testing.assert_array_equal(out.cpu().numpy().astype(np.float64), Zp)
+    np.testing.assert_array_equal(lab.cpu().numpy(), labp)
+    np.testing.assert_array_equal(best.cpu().numpy(), Zp[:, :, 0].astype(np.float32))
+
+
 def test_batch_equals_individual(ctx):
     ws = [CASES[0], CASES[1], CASES[4], CASES[6]]
     say("batch of 4 vs individual calls")
