@@ -81,20 +81,28 @@ __global__ __launch_bounds__(64) void guide_shift_final_kernel(const double* __r
 // g32 holds n + 1 planar channels [n+1][P], channel 0 being the constant
 // G_0 = 1, so the per-label kernels index the multiplier of every box channel
 // uniformly and read 16 consecutive columns of one channel with one scalar load.
+// The block's 256 pixels of g64 [P][n] are one contiguous run of 256 n
+// doubles: they are gathered in LDS and stored by consecutive lanes.
 __global__ __launch_bounds__(256) void guide_synth_kernel(
     const float* __restrict__ I, int P, MonoTable t, const double* __restrict__ shift,
     float* __restrict__ g32, double* __restrict__ g64) {
-  const int p = static_cast<int>(blockIdx.x) * 256 + threadIdx.x;
-  if (p >= P) return;
-  float iv[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int c = 0; c < t.m; ++c) iv[c] = I[static_cast<size_t>(c) * P + p];
-  g32[p] = 1.0f;
-  double* __restrict__ row = g64 + static_cast<size_t>(p) * t.n;
-  for (int k = 0; k < t.n; ++k) {
-    const double g = monomial(t, k, iv) - shift[k];
-    row[k] = g;
-    g32[static_cast<size_t>(k + 1) * P + p] = static_cast<float>(g);
+  __shared__ double st[256 * kMaxN];
+  const int p0 = static_cast<int>(blockIdx.x) * 256;
+  const int p = p0 + static_cast<int>(threadIdx.x);
+  if (p < P) {
+    float iv[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < t.m; ++c) iv[c] = I[static_cast<size_t>(c) * P + p];
+    g32[p] = 1.0f;
+    for (int k = 0; k < t.n; ++k) {
+      const double g = monomial(t, k, iv) - shift[k];
+      st[threadIdx.x * t.n + k] = g;
+      g32[static_cast<size_t>(k + 1) * P + p] = static_cast<float>(g);
+    }
   }
+  __syncthreads();
+  const int count = min(256, P - p0) * t.n;
+  double* __restrict__ dst = g64 + static_cast<size_t>(p0) * t.n;
+  for (int e = static_cast<int>(threadIdx.x); e < count; e += 256) dst[e] = st[e];
 }
 
 // ---------------------------------------------------------------------------
