@@ -324,8 +324,9 @@ __global__ __launch_bounds__(64) void invert_kernel(
 // the kLpp = 4 lanes of a quad (lane q owns rows q, q + 4, ...), so the matrix
 // stays in registers.  Values move within the quad by DPP broadcasts (plain
 // vector ALU operations, no LDS round trip).  Every lane of the quad computes
-// the same Schur complement, reduced in a fixed order.  The rank-one update
-// uses the symmetric product u_i u_j, so the stored M stays exactly symmetric.
+// the same Schur complement, reduced in a fixed order.  Each step is a single
+// rank-one update of the rows and columns in use; only the upper triangle of
+// the result is stored.
 constexpr int kLpp = 4;
 // threads per block of the lane inverse: two blocks fit a CU, so one stages
 // its window sums while the other computes
@@ -376,16 +377,20 @@ __device__ __forceinline__ void quad_bordered_inverse(EntryFn A, int q,
       default: return quad_bcast<3>(v);
     }
   };
+  // Row blocks r with kLpp * r >= kap hold no row of the current M: they are
+  // skipped (kap and r are constants once the loops are unrolled).
 #pragma unroll
   for (int kap = 1; kap < D; ++kap) {
-    // column kap of the system: lane q forms the entries j = q mod 4
+    const int KB = kap / kLpp;  // row block of the new row kap
+    // column kap of the system: lane q forms the entries j = q mod 4, j < kap
     double gq[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
+      if (kLpp * r >= kap) break;
       const int j = q + kLpp * r;
-      gq[r] = (j < kap) ? A(j, kap) : 0.0;
+      gq[r] = (kLpp * r + kLpp - 1 < kap) ? A(j, kap) : ((j < kap) ? A(j, kap) : 0.0);
     }
-    // u = M g for the owned rows
+    // u = M g for the owned rows (rows >= kap of M are zero, so is u there)
     double u[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) u[r] = 0.0;
@@ -393,33 +398,34 @@ __device__ __forceinline__ void quad_bordered_inverse(EntryFn A, int q,
     for (int j = 0; j < kap; ++j) {
       const double gj = bcast(gq[j / kLpp], j % kLpp);
 #pragma unroll
-      for (int r = 0; r < NR; ++r) u[r] = fma(M[r][j], gj, u[r]);
+      for (int r = 0; r < NR; ++r)
+        if (kLpp * r < kap) u[r] = fma(M[r][j], gj, u[r]);
     }
     double part = 0.0;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if (q + kLpp * r >= kap) u[r] = 0.0;
-      part = fma(gq[r], u[r], part);
-    }
+    for (int r = 0; r < NR; ++r)
+      if (kLpp * r < kap) part = fma(gq[r], u[r], part);
     const double inv = 1.0 / (A(kap, kap) - quad_sum(part));
-    // M <- [[M + u u^T / s, -u / s], [-u^T / s, 1 / s]]
-#pragma unroll
-    for (int j = 0; j < kap; ++j) {
-      const double uj = bcast(u[j / kLpp], j % kLpp);
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (q + kLpp * r < kap) M[r][j] = fma(u[r] * uj, inv, M[r][j]);
-      if (q == kap % kLpp) M[kap / kLpp][j] = -uj * inv;
-    }
+    // With u_kap = -1 the bordered result
+    //   [[M + u u^T / s, -u / s], [-u^T / s, 1 / s]]
+    // is the one rank-one update M += u (u / s)^T over rows and columns <= kap.
+    if (q == kap % kLpp) u[KB] = -1.0;
+    double w[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-      if (q + kLpp * r < kap) M[r][kap] = -u[r] * inv;
-    if (q == kap % kLpp) M[kap / kLpp][kap] = inv;
+      if (r <= KB) w[r] = u[r] * inv;
+#pragma unroll
+    for (int j = 0; j <= kap; ++j) {
+      const double wj = bcast(w[j / kLpp], j % kLpp);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (r <= KB) M[r][j] = fma(u[r], wj, M[r][j]);
+    }
   }
 }
 
 template <int D, int RIDGE>
-__global__ __launch_bounds__(kInvBlock) void invert_lanes_kernel(
+__global__ __launch_bounds__(kInvBlock, 2) void invert_lanes_kernel(
     const double* __restrict__ S, int H, int W, int R, double eps,
     double* __restrict__ mu_out, void* __restrict__ minv_void) {
   using MT = typename std::conditional<RIDGE != 0, double, float>::type;
@@ -532,7 +538,11 @@ __global__ __launch_bounds__(kSpdPerBlock * kLpp) void spd_inverse_lanes_kernel(
     const int i = q + kLpp * r;
     if (i < D) {
 #pragma unroll
-      for (int j = 0; j < D; ++j) O[i * D + j] = M[r][j];
+      for (int j = 0; j < D; ++j)
+        if (j >= i) {
+          O[i * D + j] = M[r][j];
+          O[j * D + i] = M[r][j];  // the lower triangle mirrors the upper
+        }
     }
   }
 }
