@@ -477,27 +477,59 @@ __global__ __launch_bounds__(kInvBlock, 2) void invert_lanes_kernel(
 
   double M[NR][D];
   quad_bordered_inverse<D>(A, q, M);
-  if (!live) return;
   constexpr int RW = minv_stride(RIDGE, NG);
-  MT* __restrict__ rec = minv_out + static_cast<size_t>(p) * RW;
-  if (!RIDGE && q == 0) {
+  if constexpr (!RIDGE) {
+    // The block's records (and window means) are gathered in LDS, over the
+    // window sums, and stored with contiguous 16-byte writes.
+    constexpr int NP = kInvBlock / kLpp;
+    static_assert(NP * RW * sizeof(float) + NP * NG * sizeof(double) <= sizeof(Ss),
+                  "records fit the staging area");
+    const int m = static_cast<int>(threadIdx.x) / kLpp;
+    double mq[NR];  // this lane's means mu_i, i = q mod 4
 #pragma unroll
-    for (int i = 0; i < NG; ++i) {
-      mu_out[static_cast<size_t>(p) * NG + i] = s[i] * invN;
-      rec[i] = static_cast<MT>(s[i] * invN);
+    for (int r = 0; r < NR; ++r)
+      if (q + kLpp * r < NG) mq[r] = s[q + kLpp * r] * invN;
+    __syncthreads();  // every lane has read its window sums
+    float* __restrict__ ob = reinterpret_cast<float*>(Ss);
+    double* __restrict__ mb = reinterpret_cast<double*>(ob + NP * RW);
+    float* __restrict__ o = ob + m * RW;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int i = q + kLpp * r;
+      if (i < NG) {
+        o[i] = static_cast<float>(mq[r]);
+        mb[m * NG + i] = mq[r];
+        const int base = NG + packed_index(i, i, D) - i;  // (i, j) lies at base + j
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+          if (j >= i) o[base + j] = static_cast<float>(M[r][j]);
+      }
     }
+    if (q == 0) {
 #pragma unroll
-    for (int e = NG + PD; e < RW; ++e) rec[e] = MT(0);
-  }
-  MT* __restrict__ o = rec + (RIDGE ? 0 : NG);
+      for (int e = NG + PD; e < RW; ++e) o[e] = 0.f;
+    }
+    __syncthreads();
+    const int p0 = static_cast<int>(blockIdx.x) * NP;
+    const int cnt = min(NP, H * W - p0);
+    const float4* __restrict__ src4 = reinterpret_cast<const float4*>(ob);
+    float4* __restrict__ dst4 = reinterpret_cast<float4*>(minv_out + static_cast<size_t>(p0) * RW);
+    for (int e = static_cast<int>(threadIdx.x); e < cnt * (RW / 4); e += kInvBlock)
+      dst4[e] = src4[e];
+    double* __restrict__ mdst = mu_out + static_cast<size_t>(p0) * NG;
+    for (int e = static_cast<int>(threadIdx.x); e < cnt * NG; e += kInvBlock) mdst[e] = mb[e];
+  } else {
+    if (!live) return;
+    MT* __restrict__ o = minv_out + static_cast<size_t>(p) * RW;
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int i = q + kLpp * r;
-    if (i < D) {
-      const int base = packed_index(i, i, D) - i;  // index of (i, j) is base + j
+    for (int r = 0; r < NR; ++r) {
+      const int i = q + kLpp * r;
+      if (i < D) {
+        const int base = packed_index(i, i, D) - i;  // index of (i, j) is base + j
 #pragma unroll
-      for (int j = 0; j < D; ++j)
-        if (j >= i) o[base + j] = static_cast<MT>(M[r][j]);
+        for (int j = 0; j < D; ++j)
+          if (j >= i) o[base + j] = static_cast<MT>(M[r][j]);
+      }
     }
   }
 }
