@@ -245,6 +245,18 @@ __global__ __launch_bounds__((NG + NG * (NG + 1) / 2 + KW - 1) / KW * 64) void m
 // The inverse is computed in float64 and stored as float32 in the covariance
 // form (the per-label product M c is float32 there) and as float64 in the ridge
 // form, whose raw-sum systems are far worse conditioned.
+// The block's window sums (64 pixels x K, contiguous) are copied to LDS with
+// coalesced direct-to-LDS loads, and its records gathered there again for
+// contiguous stores.
+template <int D, int RIDGE>
+constexpr int invert_lds_doubles() {
+  constexpr int NG = RIDGE ? D - 1 : D;
+  constexpr int K = NG + NG * (NG + 1) / 2;
+  constexpr int RW = minv_stride(RIDGE, NG);
+  constexpr int out = RIDGE ? RW : (RW * 4 + NG * 8 + 7) / 8;
+  return 64 * (K > out ? K : out);
+}
+
 template <int D, int RIDGE>
 __global__ __launch_bounds__(64) void invert_kernel(
     const double* __restrict__ S, int H, int W, int R, double eps,
@@ -254,13 +266,29 @@ __global__ __launch_bounds__(64) void invert_kernel(
   constexpr int NG = RIDGE ? D - 1 : D;             // guidance channels n
   constexpr int K = NG + NG * (NG + 1) / 2;
   constexpr int PD = D * (D + 1) / 2;
-  const int p = static_cast<int>(blockIdx.x) * 64 + threadIdx.x;
-  if (p >= H * W) return;
+  constexpr int RW = minv_stride(RIDGE, NG);
+  __shared__ double Ss[invert_lds_doubles<D, RIDGE>()];
+  const int lane = static_cast<int>(threadIdx.x);
+  const int p0 = static_cast<int>(blockIdx.x) * 64;
+  const int cnt = min(64, H * W - p0);
+  {
+    const int dwords = cnt * K * 2;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(S + static_cast<size_t>(p0) * K);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(Ss);
+    for (int base = 0; base < dwords; base += 64) {
+      const int i = min(base + lane, dwords - 1);
+      __builtin_amdgcn_global_load_lds(src + i, dst + base, 4, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  // lanes past the image work on their (unfilled) slot and store nothing
+  const int p = min(p0 + lane, H * W - 1);
   const int y = p / W;
   const int x = p - y * W;
   const double Np = static_cast<double>(window_count(x, y, W, H, R));
   const double invN = 1.0 / Np;
-  const double* s = S + static_cast<size_t>(p) * K;
+  const double* s = Ss + lane * K;
 
   double mu[NG];
 #pragma unroll
@@ -304,20 +332,34 @@ __global__ __launch_bounds__(64) void invert_kernel(
     }
     M[packed_index(kap, kap, D)] = inv;
   }
-  constexpr int RW = minv_stride(RIDGE, NG);
-  MT* __restrict__ rec = minv_out + static_cast<size_t>(p) * RW;
+  __syncthreads();  // every lane has read its window sums
+  MT* __restrict__ ob = reinterpret_cast<MT*>(Ss);
+  MT* __restrict__ rec = ob + lane * RW;
+  constexpr int M0 = RIDGE ? 0 : NG;
   if (!RIDGE) {
+    double* __restrict__ mb = reinterpret_cast<double*>(ob + 64 * RW);
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
-      mu_out[static_cast<size_t>(p) * NG + i] = mu[i];
+      mb[lane * NG + i] = mu[i];
       rec[i] = static_cast<MT>(mu[i]);
     }
 #pragma unroll
     for (int q = NG + PD; q < RW; ++q) rec[q] = MT(0);
   }
-  constexpr int M0 = RIDGE ? 0 : NG;
 #pragma unroll
   for (int q = 0; q < PD; ++q) rec[M0 + q] = static_cast<MT>(M[q]);
+  __syncthreads();
+  MT* __restrict__ dst = minv_out + static_cast<size_t>(p0) * RW;
+  if (!RIDGE) {
+    const float4* __restrict__ src4 = reinterpret_cast<const float4*>(ob);
+    float4* __restrict__ dst4 = reinterpret_cast<float4*>(dst);
+    for (int e = lane; e < cnt * (RW / 4); e += 64) dst4[e] = src4[e];
+    const double* __restrict__ mb = reinterpret_cast<const double*>(ob + 64 * RW);
+    double* __restrict__ mdst = mu_out + static_cast<size_t>(p0) * NG;
+    for (int e = lane; e < cnt * NG; e += 64) mdst[e] = mb[e];
+  } else {
+    for (int e = lane; e < cnt * RW; e += 64) dst[e] = ob[e];
+  }
 }
 
 // Large systems (D >= 11): the same recursion with the rows of M spread over
