@@ -28,17 +28,11 @@ __device__ __forceinline__ double monomial(const MonoTable& t, int k, const floa
 // is the channel mean over a fixed grid of at most 64 x 64 pixels, reduced by
 // one block in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
-// Sum over the 64 lanes of a wave by a fixed butterfly (deterministic).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 constexpr int kShiftGrid = kShiftRows;  // sample grid: at most 64 x 64 pixels
 
-// One wave per row of the sample grid (one sample per lane), then one wave
-// for the rows' partial sums.
+// One wave per row of the sample grid (one sample per lane, summed over the
+// lanes by a fixed xor butterfly, which leaves the same bits in every lane),
+// then one wave for the rows' partial sums.
 __global__ __launch_bounds__(64) void guide_shift_partial_kernel(const float* __restrict__ I,
                                                                  int H, int W, MonoTable t,
                                                                  double* __restrict__ partial) {
@@ -52,12 +46,21 @@ __global__ __launch_bounds__(64) void guide_shift_partial_kernel(const float* __
     const size_t p = static_cast<size_t>(y) * W + lane * sx;
     for (int c = 0; c < t.m; ++c) iv[c] = I[static_cast<size_t>(c) * P + p];
   }
+  // the butterflies of all channels run in lockstep (the same association
+  // per channel as one at a time), so their shuffle latencies overlap
+  double v[kMaxD];
 #pragma unroll
-  for (int k = 0; k < kMaxD; ++k) {
-    if (k < t.n) {
-      const double v = wave_sum(lane < nx ? monomial(t, k, iv) : 0.0);
-      if (lane == 0) partial[blockIdx.x * kMaxD + k] = v;
-    }
+  for (int k = 0; k < kMaxD; ++k) v[k] = (k < t.n && lane < nx) ? monomial(t, k, iv) : 0.0;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < kMaxD; ++k) v[k] += __shfl_xor(v[k], off, 64);
+  if (lane < t.n) {
+    double mine = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxD; ++k)
+      if (k == lane) mine = v[k];
+    partial[blockIdx.x * kMaxD + lane] = mine;
   }
 }
 
