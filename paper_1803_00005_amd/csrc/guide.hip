@@ -116,11 +116,11 @@ __global__ __launch_bounds__(256) void guide_synth_kernel(
 // vertical update: a lane loads the n guidance values of
 // its column of the entering and the leaving row (a few contiguous loads, all
 // in flight together) and updates the float64 running sums of the moments of
-// that column.  Up to nine channels one wave holds all K <= 54 moments; with
-// more, each of the block's waves holds KW consecutive moments (the waves
-// read the same columns, from L1).  The sums then pass through LDS,
-// transposed to lanes = moments, for the horizontal running sums and the
-// coalesced stores of S[p][k].
+// that column.  Each of the block's waves holds KW consecutive moments (two
+// waves up to nine channels, eight above; the waves read the same columns,
+// from L1).  The sums then pass through LDS, transposed to lanes = moments,
+// for the horizontal running sums and the coalesced stores of S[p][k]; the
+// output columns are split into up to four parts summed by separate threads.
 
 // coef times the moments [K0, K0 + KW) of g (g_k, then g_i g_j, i <= j, in
 // the packed order) added to the running sums vs[k - K0]
@@ -148,6 +148,9 @@ __global__ __launch_bounds__((NG + NG * (NG + 1) / 2 + KW - 1) / KW * 64) void m
   constexpr int NWM = (K + KW - 1) / KW;  // waves of the block
   constexpr int SOUT = kStrip - 2 * R;
   constexpr int TS = kStrip + 1;  // LDS row stride of the transpose (doubles)
+  // parts of the output columns summed by separate threads
+  constexpr int NSPLIT = (NWM * 64) / K < 1 ? 1 : ((NWM * 64) / K > 4 ? 4 : (NWM * 64) / K);
+  constexpr int JC = (SOUT + NSPLIT - 1) / NSPLIT;
   __shared__ double tr[K * TS];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
@@ -209,21 +212,27 @@ __global__ __launch_bounds__((NG + NG * (NG + 1) / 2 + KW - 1) / KW * 64) void m
     for (int k = 0; k < KW; ++k)
       if (wv * KW + k < K) tr[(wv * KW + k) * TS + lane] = vs[k];
     __syncthreads();
-    const int kk = static_cast<int>(threadIdx.x);
-    if (kk < K) {
-      const double* __restrict__ row = tr + kk * TS;
+    // horizontal running sums: thread t takes moment t mod K over the
+    // output columns of part t / K
+    const int t = static_cast<int>(threadIdx.x);
+    const int j0 = (t / K) * JC;
+    if (t < K * NSPLIT && j0 < SOUT) {
+      const int kk = t % K;
+      const double* __restrict__ row = tr + kk * TS + j0;
       // the output row origin is laundered so that the per-column store
       // addresses are formed as they are used, not hoisted out of the loop
-      int ox = x_out0;
-      asm volatile("" : "+s"(ox));
+      int ox = x_out0 + j0;
+      asm volatile("" : "+v"(ox));
       double* __restrict__ srow = S + (static_cast<size_t>(y) * W + ox) * K + kk;
       double hs = 0.0;
 #pragma unroll
       for (int c = 0; c <= 2 * R; ++c) hs += row[c];
 #pragma unroll
-      for (int j = 0; j < SOUT; ++j) {
-        if (j > 0) hs += row[j + 2 * R] - row[j - 1];
-        if (x_out0 + j < W) srow[static_cast<size_t>(j) * K] = hs;
+      for (int j = 0; j < JC; ++j) {
+        if (j0 + j < SOUT) {
+          if (j > 0) hs += row[j + 2 * R] - row[j - 1];
+          if (x_out0 + j0 + j < W) srow[static_cast<size_t>(j) * K] = hs;
+        }
       }
     }
     __syncthreads();
@@ -694,8 +703,8 @@ template <int R, int NG>
 static hipError_t moments_n(const double* g64, int H, int W, int target, double* S,
                                hipStream_t s) {
   constexpr int K = NG + NG * (NG + 1) / 2;
-  // one wave for up to 64 moments; above, eight waves of up to 27 moments
-  constexpr int KW = K <= 64 ? K : (K + 7) / 8;
+  // two waves for up to 64 moments; above, eight waves of up to 27 moments
+  constexpr int KW = K <= 64 ? (K + 1) / 2 : (K + 7) / 8;
   constexpr int NWM = (K + KW - 1) / KW;
   StripGrid g = strip_grid(H, W, R, 1, target);
   hipLaunchKernelGGL((moments_kernel<R, NG, KW>),
