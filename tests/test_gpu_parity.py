@@ -159,6 +159,8 @@ def test_spd_inverse_matches_lu(D):
     rel = np.abs(Mg - Mo).max(axis=(1, 2)) / np.abs(Mo).max(axis=(1, 2))
     cond = np.linalg.cond(A)
     assert np.all(rel <= 1e-15 * cond * D * 10), f"max rel {rel.max():.2e}"
+    # the full result is exactly symmetric (Prop. 1 builds a symmetric inverse)
+    np.testing.assert_array_equal(Mg, np.swapaxes(Mg, 1, 2))
 
 
 @pytest.mark.parametrize("w", [CASES[1], CASES[2], RIDGE_CASES[0]], ids=["n9", "n19", "ridge_n6"])
