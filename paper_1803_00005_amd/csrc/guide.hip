@@ -382,9 +382,10 @@ __global__ __launch_bounds__(64) void invert_kernel(
 // rank-one update of the rows and columns in use; only the upper triangle of
 // the result is stored.
 constexpr int kLpp = 4;
-// threads per block of the lane inverse: two blocks fit a CU, so one stages
-// its window sums while the other computes
-constexpr int kInvBlock = 128;
+// threads per block of the lane inverse: one wave (16 pixels); at n = 19 six
+// such blocks fit a CU's LDS, and each stages its window sums while the
+// others compute
+constexpr int kInvBlock = 64;
 
 // Value of lane K of this lane's quad.
 template <int K>
