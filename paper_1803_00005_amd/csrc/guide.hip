@@ -25,60 +25,55 @@ __device__ __forceinline__ double monomial(const MonoTable& t, int k, const floa
 // a1: the channel shifts and the synthesized guidance.  The covariance form
 // is invariant to a constant shift of each guidance channel, so any constant
 // is exact; the shift only centres the values for float32 conditioning.  It
-// is the channel mean over a fixed grid of at most 64 x 64 pixels, reduced by
+// is the channel mean over a fixed grid of at most 16 x 16 pixels, reduced by
 // one block in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
-constexpr int kShiftGrid = kShiftRows;  // sample grid: at most 64 x 64 pixels
+constexpr int kShiftGrid = kShiftRows;  // sample grid: at most 16 x 16 pixels
 
-// One wave per row of the sample grid (one sample per lane, summed over the
-// lanes by a fixed xor butterfly, which leaves the same bits in every lane),
-// then one wave for the rows' partial sums.
-__global__ __launch_bounds__(64) void guide_shift_partial_kernel(const float* __restrict__ I,
-                                                                 int H, int W, MonoTable t,
-                                                                 double* __restrict__ partial) {
+// One block of kShiftRows x kShiftRows threads, one sample each: each wave
+// sums its samples over the lanes by a fixed xor butterfly (which leaves the
+// same bits in every lane; all channels in lockstep, so the shuffle
+// latencies overlap), and the waves' sums are added in wave order.
+constexpr int kShiftThreads = kShiftGrid * kShiftGrid;
+constexpr int kShiftWaves = kShiftThreads / 64;
+
+__global__ __launch_bounds__(kShiftThreads) void guide_shift_kernel(
+    const float* __restrict__ I, int H, int W, MonoTable t, int centre,
+    double* __restrict__ shift) {
+  __shared__ double wsum[kShiftWaves * kMaxD];
   const int sy = (H + kShiftGrid - 1) / kShiftGrid, sx = (W + kShiftGrid - 1) / kShiftGrid;
-  const int nx = (W + sx - 1) / sx;
+  const int ny = (H + sy - 1) / sy, nx = (W + sx - 1) / sx;
   const size_t P = static_cast<size_t>(H) * W;
-  const int lane = threadIdx.x;
-  const int y = static_cast<int>(blockIdx.x) * sy;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int lane = tid & 63, wv = tid >> 6;
+  const int gy = tid / kShiftGrid, gx = tid % kShiftGrid;
+  const bool in = gy < ny && gx < nx;
   float iv[4] = {0.f, 0.f, 0.f, 0.f};
-  if (lane < nx) {
-    const size_t p = static_cast<size_t>(y) * W + lane * sx;
+  if (in) {
+    const size_t p = static_cast<size_t>(gy * sy) * W + gx * sx;
     for (int c = 0; c < t.m; ++c) iv[c] = I[static_cast<size_t>(c) * P + p];
   }
-  // the butterflies of all channels run in lockstep (the same association
-  // per channel as one at a time), so their shuffle latencies overlap
   double v[kMaxD];
 #pragma unroll
-  for (int k = 0; k < kMaxD; ++k) v[k] = (k < t.n && lane < nx) ? monomial(t, k, iv) : 0.0;
+  for (int k = 0; k < kMaxD; ++k) v[k] = (k < t.n && in) ? monomial(t, k, iv) : 0.0;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1)
 #pragma unroll
     for (int k = 0; k < kMaxD; ++k) v[k] += __shfl_xor(v[k], off, 64);
-  if (lane < t.n) {
+  if (lane < kMaxD) {
     double mine = 0.0;
 #pragma unroll
     for (int k = 0; k < kMaxD; ++k)
       if (k == lane) mine = v[k];
-    partial[blockIdx.x * kMaxD + lane] = mine;
+    wsum[wv * kMaxD + lane] = mine;
   }
-}
-
-__global__ __launch_bounds__(64) void guide_shift_final_kernel(const double* __restrict__ partial,
-                                                               int H, int W, int n, int centre,
-                                                               double* __restrict__ shift) {
-  const int sy = (H + kShiftGrid - 1) / kShiftGrid, sx = (W + kShiftGrid - 1) / kShiftGrid;
-  const int ny = (H + sy - 1) / sy, nx = (W + sx - 1) / sx;
-  const int k = threadIdx.x;
-  if (k >= n) return;
-  // all row loads issued together, then summed in row order
-  double v[kShiftRows];
+  __syncthreads();
+  if (tid < t.n) {
+    double tot = 0.0;
 #pragma unroll
-  for (int r = 0; r < kShiftRows; ++r) v[r] = r < ny ? partial[r * kMaxD + k] : 0.0;
-  double tot = 0.0;
-#pragma unroll
-  for (int r = 0; r < kShiftRows; ++r) tot += v[r];
-  shift[k] = centre ? tot / static_cast<double>(ny * nx) : 0.0;
+    for (int w = 0; w < kShiftWaves; ++w) tot += wsum[w * kMaxD + tid];
+    shift[tid] = centre ? tot / static_cast<double>(ny * nx) : 0.0;
+  }
 }
 
 // g32 holds n + 1 planar channels [n+1][P], channel 0 being the constant
@@ -681,12 +676,9 @@ __global__ __launch_bounds__(64) void spd_inverse_kernel(const double* __restric
 
 }  // namespace
 
-hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t, double* partial,
-                             double* shift, bool centre, hipStream_t s) {
-  const int sy = (H + kShiftGrid - 1) / kShiftGrid;
-  const int ny = (H + sy - 1) / sy;
-  hipLaunchKernelGGL(guide_shift_partial_kernel, dim3(ny), dim3(64), 0, s, I, H, W, t, partial);
-  hipLaunchKernelGGL(guide_shift_final_kernel, dim3(1), dim3(64), 0, s, partial, H, W, t.n,
+hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t, double* shift,
+                             bool centre, hipStream_t s) {
+  hipLaunchKernelGGL(guide_shift_kernel, dim3(1), dim3(kShiftThreads), 0, s, I, H, W, t,
                      centre ? 1 : 0, shift);
   return hipGetLastError();
 }

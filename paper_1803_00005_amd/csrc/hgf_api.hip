@@ -199,8 +199,6 @@ Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
   pl.chunks_per_launch = static_cast<int>(
       std::max<size_t>(1, std::min<size_t>(chunks_total, kWsCapBytes / pl.ws_chunk_bytes)));
   size_t off = 0;
-  pl.off_partial = off;
-  off = align_up(off + sizeof(double) * kShiftRows * kMaxD);
   pl.off_shift = off;
   off = align_up(off + sizeof(double) * kMaxD);
   pl.off_g64 = off;
@@ -349,8 +347,8 @@ hgf_status run_guide(hgf_context* ctx, const Plan& pl, const float* guide, void*
                      hipStream_t s) {
   {
     Stage st(ctx, 0, s);
-    HGF_TRY(launch_guide_mean(guide, pl.H, pl.W, pl.table, at<double>(ws, pl.off_partial),
-                              at<double>(ws, pl.off_shift), pl.reg == HGF_REG_COVARIANCE, s),
+    HGF_TRY(launch_guide_mean(guide, pl.H, pl.W, pl.table, at<double>(ws, pl.off_shift),
+                              pl.reg == HGF_REG_COVARIANCE, s),
             "guide_mean");
   }
   {

@@ -35,12 +35,12 @@ bool radius_supported(int R);
 bool config_supported(int n, int R, int reg);
 
 // a1 + shift: guidance channel shifts (covariance form: each channel's mean
-// over a fixed grid of at most 64 x 64 pixels, an exact reformulation since
+// over a fixed grid of at most 16 x 16 pixels, an exact reformulation since
 // the window covariance does not see a constant offset; ridge form: 0).
-hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t, double* partial,
-                             double* shift, bool centre, hipStream_t s);
-// Rows of the shift sample grid (the partial sums need kShiftRows x kMaxD doubles).
-constexpr int kShiftRows = 64;
+hipError_t launch_guide_mean(const float* I, int H, int W, const MonoTable& t, double* shift,
+                             bool centre, hipStream_t s);
+// Rows (and columns) of the shift sample grid.
+constexpr int kShiftRows = 16;
 // a1: synthesized (shifted) guidance: float64 [P][n] and planar float32
 // [n+1][P] with the constant channel G_0 = 1 first (g32 points at channel 0;
 // the allocation has kGPad floats before and after).

@@ -48,7 +48,7 @@ struct Plan {
   int n = 0, D = 0, PD = 0, K = 0, P = 0, H = 0, W = 0, R = 0, L = 0, reg = 0, bf16 = 0;
   double eps = 0.0;
   int chunks_total = 0, chunks_per_launch = 0;
-  size_t off_partial = 0, off_shift = 0, off_g64 = 0, off_g32 = 0, off_mu = 0, off_minv = 0;
+  size_t off_shift = 0, off_g64 = 0, off_g32 = 0, off_mu = 0, off_minv = 0;
   size_t off_x = 0, off_keys = 0, total = 0;
   size_t ws_chunk_bytes = 0;
   MonoTable table{};
