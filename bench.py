@@ -609,8 +609,8 @@ def main():
                          "byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the filter would shard by labels or image strips; see the design notes)",
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
+              "(across GPUs the filter would shard by label ranges or image strips)",
               file=sys.stderr)
         sys.exit(2)
     secondary = [] if args.secondary == "none" else [x for x in args.secondary.split(",") if x]

@@ -93,3 +93,17 @@ def test_reserved_field_must_be_zero():
 def test_ld_smaller_than_labels_rejected():
     with pytest.raises(hgf.HGFError):
         hgf.workspace_size(_p(cost_ld=2))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with a message
+    before anything touches a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    proc = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2",
+                           "--steps", "1", "--warmup", "0"],
+                          capture_output=True, text=True, timeout=300, cwd=root)
+    assert proc.returncode == 2
+    assert "one GPU" in proc.stderr
+    assert proc.stdout.strip() == ""
