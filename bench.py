@@ -43,8 +43,11 @@ from paper_1803_00005_amd.build_lib import source_hash  # noqa: E402
 METRIC = "filtered Mpixel·labels/s (n=9,19) at stated error vs FP64; HBM GB/s; p99"
 UNIT = "Mpixel·labels/s"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
+# MI355X's published FP32 vector peak (packed / dual-issue FP32 counted)
+FP32_PEAK_TFLOPS = 157.3
 # FMA rate of the vector ALU without packed FP32: 256 CU x 4 SIMD x 16 lanes x
-# 2 flop x 2.4 GHz; float64 FMAs issue at the same rate on this chip.
+# 2 flop x 2.4 GHz; float64 FMAs issue at the same rate on this chip.  The
+# kernels are built without packed FP32, so this is the rate they can reach.
 VALU_PEAK_TFLOPS = 78.6
 DEFAULT_WORKLOAD = "voronoi450x375_n9_L60"
 STAGES = ["guide_mean", "guide_synth", "guide_moments", "guide_invert", "coef", "out_wta",
@@ -65,7 +68,7 @@ def stage_model(w: synth.Workload, reg: str = "covariance"):
     D = n + 1 if reg == "ridge" else n
     PD = D * (D + 1) // 2
     K = n + n * (n + 1) // 2
-    esz = 2 if w.cost_dtype == "bf16" else 4
+    esz = 4 if w.cost_dtype == "f32" else 2
     m = w.guide_channels
     return {
         # window sums of the n + 1 products (n mults, 4 running-sum adds per channel),
@@ -80,6 +83,56 @@ def stage_model(w: synth.Workload, reg: str = "covariance"):
         "guide_synth": dict(flops=P * n * 3, bytes=P * (4 * m + 8 * n + 4 * (n + 1))),
         "guide_mean": dict(flops=P * n * 3, bytes=P * 4 * m),
         "wta_keys": dict(flops=0, bytes=P * 8 * 3 + P * 4),
+    }
+
+
+def method_model(w: synth.Workload):
+    """The method's own work per px·label, independent of any kernel design.
+
+    Bytes: the algorithmic minimum that must cross HBM: read the cost, write
+    Z, plus per pixel the guidance read (4 m) and the label write (4) spread
+    over the L labels.  Flops: the coefficient product a = M c (2 n^2), the
+    two separable running-sum box filters of the n + 1 product and
+    coefficient channels (8 (n + 1)), the products, covariances, intercept and
+    output (7 n), plus the per-pixel guidance statistics and inverse
+    (n^3 + 4 n (n + 3) / 2) spread over the labels."""
+    n, L, m = w.n, w.labels, w.guide_channels
+    e = 4 if w.cost_dtype == "f32" else 2
+    return {"bytes": e + 4 + (4 * m + 4) / L,
+            "flops": 2 * n * n + 8 * (n + 1) + 7 * n + (n ** 3 + 4 * n * (n + 3) / 2) / L}
+
+
+def method_roofline(w, name, units, ms_per_launch, staged, traffic, ms_step):
+    """Roofline position of the dominant kernel: the method's minimum bytes
+    and flops of the units (px·labels) one launch processes, over that
+    kernel's mean launch time, against 8 TB/s and 157.3 TFLOP/s.  At minimum
+    traffic the method is ALU-bound (its intensity is above the ridge), which
+    "binding_roof" names; "frac" is the HBM fraction of the algorithmic bytes.
+    The staged bytes (the design's own traffic between its kernels), the
+    non-packed vector peak and the measured counter traffic are separate
+    fields."""
+    mm = method_model(w)
+    sec = ms_per_launch * 1e-3
+    gbs = units * mm["bytes"] / sec / 1e9
+    tfs = units * mm["flops"] / sec / 1e12
+    intensity = mm["flops"] / mm["bytes"]
+    ridge = FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    step_s = ms_step * 1e-3
+    return {
+        "kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+        "units_per_launch": units, "unit_of_work": "px·label",
+        "algorithmic_bytes_per_unit": mm["bytes"], "algorithmic_flops_per_unit": mm["flops"],
+        "ms_per_launch": ms_per_launch,
+        "alu": {"achieved": tfs, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tfs / FP32_PEAK_TFLOPS,
+                "frac_of_nonpacked_peak": tfs / VALU_PEAK_TFLOPS,
+                "nonpacked_peak": VALU_PEAK_TFLOPS},
+        "binding_roof": "alu" if intensity > ridge else "hbm",
+        "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+        "whole_step": {"hbm_frac": units * mm["bytes"] / step_s / 1e9 / HBM_PEAK_GBS,
+                       "alu_frac": units * mm["flops"] / step_s / 1e12 / FP32_PEAK_TFLOPS},
+        "staged": staged,
     }
 
 
@@ -198,13 +251,14 @@ def sampled_error(w: synth.Workload, guide, cost, Z, lab, k: int = 14, seed: int
 # plain form: one image per call
 # ----------------------------------------------------------------------------
 
-def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True, autotune=True):
+def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True, autotune=True, stats="f32"):
     import torch
 
     from paper_1803_00005_amd import hgf
     dev = g_d.device
     p = hgf.make_params(w.height, w.width, w.labels, radius=w.radius, eps=w.eps, degree=w.degree,
-                        guide_channels=w.guide_channels, basis=w.basis, cost_dtype=w.cost_dtype)
+                        guide_channels=w.guide_channels, basis=w.basis, cost_dtype=w.cost_dtype,
+                        stats_dtype=stats)
     ws = torch.empty(hgf.workspace_size(p), dtype=torch.uint8, device=dev)
     Z = torch.empty((w.height, w.width, w.labels), dtype=torch.float32, device=dev)
     lab = torch.empty((w.height, w.width), dtype=torch.int32, device=dev)
@@ -212,15 +266,15 @@ def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True, autotune=True)
 
     def step():
         ctx.filter(g_d, c_d, radius=w.radius, eps=w.eps, degree=w.degree, basis=w.basis,
-                   out=Z, labels=lab, workspace=ws, stream=stream)
+                   stats_dtype=stats, out=Z, labels=lab, workspace=ws, stream=stream)
 
     if autotune:
         # untimed set-up: the strip decomposition for this size class is chosen
         # by timing the candidates on these inputs (hgf_autotune)
         ctx.autotune(g_d, c_d, radius=w.radius, eps=w.eps, degree=w.degree, basis=w.basis,
-                     stream=stream)
+                     stats_dtype=stats, stream=stream)
     tuned = [r for r in ctx.tune_entries() if r[1] == w.n and r[2] == w.radius
-             and r[4] == (1 if w.cost_dtype == "bf16" else 0)
+             and r[4] == hgf.COST_DTYPES[w.cost_dtype]
              and r[5] == (w.pixels.bit_length() - 1)]
     for _ in range(warmup):
         step()
@@ -267,35 +321,47 @@ def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True, autotune=True)
     if rows:
         dom = max(rows, key=lambda r: r["ms_per_step"])
         cnt = stages[dom["stage"]][1]
-        mdl = {k: v / (cnt / steps) for k, v in model[dom["stage"]].items()}
-        roof = roofline_of(KERNEL_NAMES.get(dom["stage"], dom["stage"]), mdl,
-                           dom["ms_per_launch"], measured_traffic(w.name, dom["stage"]))
+        per_step = cnt / steps
+        mdl = {k: v / per_step for k, v in model[dom["stage"]].items()}
+        st = roofline_of(KERNEL_NAMES.get(dom["stage"], dom["stage"]), mdl,
+                         dom["ms_per_launch"], None)
+        staged = {"bytes_per_launch": mdl["bytes"], "flops_per_launch": mdl["flops"],
+                  "bound": st["bound"], "achieved": st["achieved"], "unit": st["unit"],
+                  "peak": st["peak"], "frac": st["frac"]}
+        roof = method_roofline(w, KERNEL_NAMES.get(dom["stage"], dom["stage"]),
+                               w.pixel_labels / per_step, dom["ms_per_launch"], staged,
+                               measured_traffic(w.name, dom["stage"]), ms)
     return {"ms": ms, "ms_stage_timed": ms_staged, "stages": rows, "roofline": roof, "Z": Z,
             "labels": lab,
             "tuning": {["coef", "out", "moments"][r[0]]: r[6] for r in tuned}}
 
 
+N19_FORMS = [("voronoi1242x375_n19_L128", "f32"), ("voronoi1242x375_n19_L128", "f64"),
+             ("voronoi1242x375_n19_L128_bf16", "f64"), ("voronoi1242x375_n19_L128_f16", "f64")]
+
+
 def secondary_n19(ctx, steps, warmup, check, autotune=True):
+    """The degree-3 workload: float32 costs with the float32 and the float64
+    solve, and the precision forms (bfloat16 / float16 costs, float64 solve)."""
     import torch
     out = []
-    for name in ("voronoi1242x375_n19_L128", "voronoi1242x375_n19_L128_bf16"):
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+    for name, stats in N19_FORMS:
         w = synth.WORKLOADS[name]
-        say(f"n19: {name}")
+        say(f"n19: {name}, {stats} solve")
         guide, cost = synth.make_workload(w)
         g_d = torch.from_numpy(guide).cuda()
-        c_d = torch.from_numpy(cost).cuda()
-        if w.cost_dtype == "bf16":
-            c_d = c_d.to(torch.bfloat16)
-        r = run_plain(ctx, w, g_d, c_d, steps, warmup, autotune=autotune)
+        c_d = torch.from_numpy(cost).cuda().to(tdt[w.cost_dtype])
+        r = run_plain(ctx, w, g_d, c_d, steps, warmup, autotune=autotune, stats=stats)
         rec = {"form": "plain", "workload": w.name, "value": w.pixel_labels / r["ms"] / 1e3,
                "tuning": {"target_blocks": r["tuning"]},
                "unit": UNIT, "ms_per_step": r["ms"], "n": w.n, "labels": w.labels,
-               "cost_dtype": w.cost_dtype, "roofline": r["roofline"], "stages": r["stages"],
-               "ms_per_step_stage_timed": r["ms_stage_timed"]}
+               "cost_dtype": w.cost_dtype, "stats_dtype": stats, "roofline": r["roofline"],
+               "stages": r["stages"], "ms_per_step_stage_timed": r["ms_stage_timed"]}
         if check:
             rec["error"] = sampled_error(w, guide, cost, r["Z"], r["labels"])
         out.append(rec)
-        say(f"n19: {name} {r['ms']:.3f} ms/step")
+        say(f"n19: {name} {stats} {r['ms']:.3f} ms/step")
         del g_d, c_d, r
         torch.cuda.empty_cache()
     return out
@@ -635,9 +701,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     g_d = torch.from_numpy(guide).to(dev)
-    c_d = torch.from_numpy(cost).to(dev)
-    if w.cost_dtype == "bf16":
-        c_d = c_d.to(torch.bfloat16)
+    c_d = torch.from_numpy(cost).to(dev).to(
+        {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[w.cost_dtype])
     ctx = hgf.Context(0)
     from paper_1803_00005_amd import tune_table
     tune_file = args.tune_file if args.tune_file is not None else (

@@ -29,11 +29,18 @@
  *     stream).  Argument errors are detected on the host before anything is
  *     enqueued; launch errors are returned at once; faults inside kernels
  *     surface at the caller's next synchronisation.
- *   - Every call returns an hgf_status; no C++ exception crosses the ABI.
- *     hgf_last_error() returns a thread-local detail string.
- *   - A context must not be used from two host threads at once.
- *   - Results are deterministic: for fixed parameters they do not depend on
- *     the stream, on other images in a batch, or on label chunking.
+ *   - Every call returns an hgf_status; no C++ exception crosses the ABI
+ *     (a failed host allocation returns HGF_E_NOMEM).  hgf_last_error()
+ *     returns the detail string of the context's last failed call.
+ *   - A context must not be used from two host threads at once.  Calls that
+ *     use context-owned memory (a NULL workspace, a resident guide) must
+ *     not overlap on two streams: they share that memory.
+ *   - Results are deterministic: for fixed parameters and tuning table they
+ *     do not depend on the stream, on other images in a batch or the served
+ *     mix, on how the labels are split into chunks (hgf_guide_filter) or on
+ *     the launch-group size (hgf_set_group_bytes).
+ *   - Compiled set: n = 1..19 guidance channels, radius 0..9, every cost
+ *     dtype, both solve precisions; the ridge form with float32 costs.
  */
 #ifndef HGF_H
 #define HGF_H
@@ -54,7 +61,10 @@ typedef enum {
   HGF_E_BUSY = -5         /* the serving queue is full */
 } hgf_status;
 
-typedef enum { HGF_F32 = 0, HGF_BF16 = 1 } hgf_dtype;
+/* Element types.  Costs may be float32, bfloat16 or float16 (converted to
+ * float32 on load; every sum and product runs in float32 or wider).  The
+ * per-pixel solve is applied in float32 or float64 (stats_dtype below). */
+typedef enum { HGF_F32 = 0, HGF_BF16 = 1, HGF_F16 = 2, HGF_F64 = 3 } hgf_dtype;
 
 /* Polynomial guidance basis (Sec. 4.2).
  *   MONOMIAL: every monomial of total degree 1..d of the m channels, graded
@@ -81,10 +91,19 @@ typedef struct {
   int32_t radius;          /* r >= 0: window side 2r + 1 */
   int32_t num_labels;      /* L >= 1 */
   double eps;              /* > 0: eps (COVARIANCE) or lambda (RIDGE) */
-  int32_t cost_dtype;      /* hgf_dtype of the cost volume */
+  int32_t cost_dtype;      /* hgf_dtype of the cost volume: HGF_F32, HGF_BF16 or HGF_F16 */
   int32_t cost_ld;         /* label stride of cost (0 = num_labels) */
   int32_t out_ld;          /* label stride of out  (0 = num_labels) */
-  int32_t reserved;        /* must be 0 */
+  int32_t stats_dtype;     /* precision of the per-pixel solve (a3, a5).  The
+                            * guidance window statistics and the inverse are
+                            * always computed in float64; then
+                            *   HGF_F32 (0): the inverse and window means are
+                            *     stored in float32 and the coefficient
+                            *     product a = M c runs in float32;
+                            *   HGF_F64: they are stored in float64 and c, a
+                            *     and b are formed in float64 (for the
+                            *     ill-conditioned systems of large n).
+                            * The ridge form always uses float64. */
 } hgf_params;
 
 typedef struct hgf_context hgf_context;
@@ -104,8 +123,17 @@ hgf_status hgf_create(int32_t device, size_t hbm_budget_bytes, hgf_context** out
 void hgf_destroy(hgf_context* ctx);
 
 /* Bytes of device workspace hgf_filter needs for these parameters, with the
- * label chunks it processes per launch.  Host only; validates params. */
+ * label chunks it processes per launch under the default launch-group size.
+ * Host only; validates params. */
 hgf_status hgf_workspace_size(const hgf_params* params, size_t* bytes);
+
+/* Upper bound of the coefficient workspace of one launch group (the float32
+ * coefficients a, b of the labels filtered by one pair of per-label launches,
+ * (n + 1) * 256 bytes per pixel and 64-label chunk).  Default 12 GiB; 0
+ * restores it.  Labels that do not fit run in further launch groups, one
+ * after another; the results do not change.  A smaller bound lowers the
+ * workspace a call needs below hgf_workspace_size(). */
+hgf_status hgf_set_group_bytes(hgf_context* ctx, size_t bytes);
 
 /* The whole hot path on one image (Fig. 2 of the paper for every slice):
  * guidance synthesis, guidance box statistics, per-pixel inverse (Prop. 1),
@@ -285,7 +313,10 @@ hgf_status hgf_stage_times(hgf_context* ctx, double* ms, int32_t* launches,
                            int32_t max_stages);
 
 const char* hgf_status_string(hgf_status status);
-const char* hgf_last_error(void);
+/* Detail string of the last failed call made with this context (NULL: of the
+ * last failed call of this thread that took no context, e.g.
+ * hgf_workspace_size).  Valid until the next call with the same context. */
+const char* hgf_last_error(const hgf_context* ctx);
 
 #ifdef __cplusplus
 }

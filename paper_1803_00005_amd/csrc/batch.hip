@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -41,7 +42,8 @@ hgf_status ensure_workers(hgf_context* ctx, int nstreams, const std::vector<size
   }
   for (int k = 0; k < nstreams; ++k) {
     if (ctx->worker_ws_bytes[k] >= need[k]) continue;
-    (void)hipDeviceSynchronize();   // the old buffer may be in use by queued work
+    // the old buffer may be in use by the last graph launch
+    wait_used(ctx->batch_done);
     ctx->graph.reset();             // a cached graph refers to the old buffer
     ctx_free(ctx, ctx->worker_ws[k], ctx->worker_ws_bytes[k]);
     ctx->worker_ws[k] = nullptr;
@@ -73,10 +75,9 @@ void hgf_release_batch_resources(hgf_context* ctx) {
   ctx->worker_ws_bytes.clear();
 }
 
-extern "C" hgf_status hgf_filter_batch(hgf_context* ctx, int32_t count, const hgf_params* params,
-                                       const float* const* guides, const void* const* costs,
-                                       float* const* outs, int32_t* const* labels,
-                                       void* hip_stream) {
+static hgf_status filter_batch(hgf_context* ctx, int32_t count, const hgf_params* params,
+                               const float* const* guides, const void* const* costs,
+                               float* const* outs, int32_t* const* labels, void* hip_stream) {
   if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
   if (count < 0) return fail(HGF_E_INVALID, "count < 0");
   if (count == 0) return HGF_OK;
@@ -86,14 +87,18 @@ extern "C" hgf_status hgf_filter_batch(hgf_context* ctx, int32_t count, const hg
   for (int i = 0; i < count; ++i) {
     MonoTable t;
     const hgf_status st = validate(&params[i], &t);
-    if (st != HGF_OK) return fail(st, "image " + std::to_string(i) + ": " + hgf_last_error());
+    if (st != HGF_OK) {
+      char detail[400];
+      std::snprintf(detail, sizeof(detail), "%s", thread_error());
+      return fail(st, "image %d: %s", i, detail);
+    }
     if (guides[i] == nullptr || costs[i] == nullptr)
-      return fail(HGF_E_INVALID, "image " + std::to_string(i) + ": guide or cost is NULL");
+      return fail(HGF_E_INVALID, "image %d: guide or cost is NULL", i);
     float* o = outs != nullptr ? outs[i] : nullptr;
     int32_t* l = labels != nullptr ? labels[i] : nullptr;
     if (o == nullptr && l == nullptr)
-      return fail(HGF_E_INVALID, "image " + std::to_string(i) + ": nothing to compute");
-    plans[i] = make_plan(&params[i], t, (params[i].num_labels + 63) / 64);
+      return fail(HGF_E_INVALID, "image %d: nothing to compute", i);
+    plans[i] = make_plan(&params[i], t, (params[i].num_labels + 63) / 64, ctx->group_bytes);
   }
   // largest-first assignment of images to worker streams
   const int nstreams = std::min<int>(kBatchStreams, count);
@@ -173,5 +178,14 @@ extern "C" hgf_status hgf_filter_batch(hgf_context* ctx, int32_t count, const hg
     ctx->graph = std::move(g);
   }
   HGF_TRY(hipGraphLaunch(ctx->graph->exec, s), "hipGraphLaunch");
-  return HGF_OK;
+  return mark_used(&ctx->batch_done, s);
+}
+
+extern "C" hgf_status hgf_filter_batch(hgf_context* ctx, int32_t count, const hgf_params* params,
+                                       const float* const* guides, const void* const* costs,
+                                       float* const* outs, int32_t* const* labels,
+                                       void* hip_stream) {
+  return guarded(ctx, [&] {
+    return filter_batch(ctx, count, params, guides, costs, outs, labels, hip_stream);
+  });
 }

@@ -7,7 +7,9 @@
 //   covariance:  c = (T - mu U) / N_p,  a = M_p c,  b = U / N_p - a . mu
 //   ridge:       [b; a] = M_p [U; T]               (M_p of the (n+1) system)
 // with M_p the per-pixel inverse computed once per image.  The coefficient
-// images [b, a_1..a_n] go to a float32 workspace [chunk][P][n+1][64].
+// images [b, a_1..a_n] go to a float32 workspace [chunk][P][n+1][64].  The
+// covariance solve runs in float32 from float32 records or in float64 from
+// float64 records (the solve mode); the ridge solve runs in float64.
 //
 // Mapping (gfx950, wave64): the 64 lanes of a wave are 64 labels of one
 // pixel.  Everything per-pixel (M_p, mu_p, G(p), N_p) is wave-uniform: M_p and
@@ -45,12 +47,12 @@ constexpr int coef_block_waves(int nw) { return nw >= 8 ? (nw + 3) / 4 * 4 : nw;
 
 // LDS of a block besides the transposed window sums: the staged inverses of
 // one row and two staged cost rows.
-template <int SOUT, int SIN, int NG, int RIDGE>
+template <int SOUT, int SIN, int NG, int MODE>
 constexpr int coef_fixed_lds_bytes();
 
-template <int NCH, int SOUT, int SIN, int RIDGE>
+template <int NCH, int SOUT, int SIN, int MODE>
 constexpr int coef_column_chunk() {
-  constexpr int avail = 160 * 1024 - coef_fixed_lds_bytes<SOUT, SIN, NCH - 1, RIDGE>();
+  constexpr int avail = 160 * 1024 - coef_fixed_lds_bytes<SOUT, SIN, NCH - 1, MODE>();
   constexpr int budget = coef_lds_bytes(NCH) < avail ? coef_lds_bytes(NCH) : avail;
   int oc = budget / (NCH * 64 * 4);
   if (oc > SOUT) oc = SOUT;
@@ -60,11 +62,11 @@ constexpr int coef_column_chunk() {
 }
 
 // Cost rows pass through LDS: a slot holds the SIN state columns of one row,
-// 64 labels each, one 32-bit word per (column, label); a bfloat16 cost lands
-// in the low half of its word.  The copies are direct global-to-LDS loads
+// 64 labels each, one 32-bit word per (column, label).  The copies are direct global-to-LDS loads
 // (no registers), issued cooperatively by all waves of the block one row
 // step ahead of their use, so the vertical update reads LDS instead of
-// waiting on global memory.
+// waiting on global memory.  A 16-bit cost (bfloat16 or float16) lands in
+// the low half of its word.
 template <bool CHECK, int SIN, int NWB, typename TIN>
 __device__ __forceinline__ void stage_cost_row(const TIN* __restrict__ cost, int cost_ld, int yy,
                                                int xsl, int W, int labc, float* __restrict__ slot,
@@ -102,7 +104,7 @@ __device__ __forceinline__ void stage_guide_row(const float* __restrict__ g32, s
 template <typename TIN>
 __device__ __forceinline__ float lds_cost(const float* __restrict__ slot, int i) {
   if constexpr (sizeof(TIN) == 2) {
-    return bf16_to_float(reinterpret_cast<const uint16_t*>(slot)[2 * i]);
+    return cost_bits_to_float<TIN>(reinterpret_cast<const uint16_t*>(slot)[2 * i]);
   } else {
     return slot[i];
   }
@@ -187,15 +189,15 @@ __device__ __forceinline__ void stage_dwords(const uint32_t* __restrict__ src,
 
 // Dwords of LDS for the stored inverses (covariance form: the solve records
 // with the window means) of one row of a strip, rounded up to whole waves.
-template <int SOUT, int NG, int RIDGE>
+template <int SOUT, int NG, int MODE>
 constexpr int coef_stage_dwords() {
-  constexpr int m = SOUT * minv_stride(RIDGE, NG) * (RIDGE ? 2 : 1);
+  constexpr int m = SOUT * minv_stride(MODE, NG) * (minv_elem_bytes(MODE) / 4);
   return (m + 63) / 64 * 64;
 }
 
-template <int SOUT, int SIN, int NG, int RIDGE>
+template <int SOUT, int SIN, int NG, int MODE>
 constexpr int coef_fixed_lds_bytes() {
-  return coef_stage_dwords<SOUT, NG, RIDGE>() * 4 + 2 * SIN * 64 * 4 + 2 * (NG + 1) * 64 * 4;
+  return coef_stage_dwords<SOUT, NG, MODE>() * 4 + 2 * SIN * 64 * 4 + 2 * (NG + 1) * 64 * 4;
 }
 
 // Reads element e of a float record at 16-byte unit `base` of an LDS array,
@@ -225,7 +227,25 @@ struct RecordReader {
   }
 };
 
-template <int R, int CPW, int NG, int RIDGE, typename TIN, int SIN, bool CHECK>
+// The same for float64 records: one 16-byte load per pair of elements.
+struct RecordReader64 {
+  const double2* __restrict__ lds2;
+  int base;
+  double2 cur;
+  int k = -1;
+  __device__ __forceinline__ RecordReader64(const double2* a, int b) : lds2(a), base(b) {
+    asm volatile("" : "+v"(base));
+  }
+  __device__ __forceinline__ double operator()(int e) {
+    if (e / 2 != k) {
+      k = e / 2;
+      cur = lds2[base + k];
+    }
+    return (e % 2) == 0 ? cur.x : cur.y;
+  }
+};
+
+template <int R, int CPW, int NG, int MODE, typename TIN, int SIN, bool CHECK>
 __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cost_ld,
                                            const float* __restrict__ g32,
                                            const void* __restrict__ minv_void,
@@ -237,13 +257,13 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
   constexpr int NCH = NG + 1;
   constexpr int NW = (NCH + CPW - 1) / CPW;
   constexpr int NWB = coef_block_waves(NW);
+  constexpr bool RIDGE = MODE == kSolveRidge;
   constexpr int D = RIDGE ? NG + 1 : NG;
-  constexpr int PD = D * (D + 1) / 2;
-  using MT = typename std::conditional<RIDGE != 0, double, float>::type;
+  using MT = typename std::conditional<MODE != kSolveCov32, double, float>::type;
   const MT* __restrict__ minv = static_cast<const MT*>(minv_void);
   // inverse elements read from LDS per scheduling block of the product
-  constexpr int MBLK = RIDGE ? 8 : 16;
-  constexpr int OC = coef_column_chunk<NCH, SOUT, SIN, RIDGE>();
+  constexpr int MBLK = MODE == kSolveCov32 ? 16 : 8;
+  constexpr int OC = coef_column_chunk<NCH, SOUT, SIN, MODE>();
   constexpr int NCB = (SOUT + OC - 1) / OC;
   const size_t P = static_cast<size_t>(H) * W;
 
@@ -264,7 +284,7 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
 
   // this row's stored inverses (covariance form: solve records [SOUT][RW]),
   // staged in LDS at the start of the row step
-  constexpr int RW = minv_stride(RIDGE, NG);
+  constexpr int RW = minv_stride(MODE, NG);
   const MT* __restrict__ sm = reinterpret_cast<const MT*>(stage);
 
   auto solve_store = [&](int x, int y, int q, int qx) {
@@ -274,7 +294,7 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
     for (int ch = 0; ch < NCH; ++ch) T[ch] = lds[(q * NCH + ch) * 64 + lane];
     const MT* __restrict__ mp = sm + qx * RW;
     float* __restrict__ o = wsc + p * NCH * 64 + lane;
-    if (!RIDGE) {
+    if constexpr (MODE == kSolveCov32) {
       // c = (T - mu U) / N, a = M c, b = U / N - a . mu, all float32: T is
       // float32 already and each fused multiply-add rounds once, so c and b
       // carry rounding errors of the order of T's own.
@@ -309,6 +329,39 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
       o[0] = b;
 #pragma unroll
       for (int i = 0; i < NG; ++i) o[(i + 1) * 64] = av[i];
+    } else if constexpr (MODE == kSolveCov64) {
+      // the same in float64, from the float64 record: c = (T - mu U) / N,
+      // a = M c, b = U / N - a . mu; only T itself is float32
+      const double invN = 1.0 / static_cast<double>(window_count(x, y, W, H, R));
+      const double U = static_cast<double>(T[0]);
+      const double2* __restrict__ st2 = reinterpret_cast<const double2*>(stage);
+      RecordReader64 rd(st2, qx * (RW / 2));
+      double c[NG];
+      double av[NG];
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+        c[i] = fma(-rd(i), U, static_cast<double>(T[i + 1])) * invN;
+        av[i] = 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < NG; ++i) {
+#pragma unroll
+        for (int j = i; j < NG; ++j) {
+          const int qq = packed_index(i, j, D);
+          if ((NG + qq) % MBLK == 0) __builtin_amdgcn_sched_barrier(0);
+          const double m = rd(NG + qq);
+          av[i] = fma(m, c[j], av[i]);
+          if (j != i) av[j] = fma(m, c[i], av[j]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      RecordReader64 rm(st2, qx * (RW / 2));
+      double b = U * invN;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) b = fma(-av[i], rm(i), b);
+      o[0] = static_cast<float>(b);
+#pragma unroll
+      for (int i = 0; i < NG; ++i) o[(i + 1) * 64] = static_cast<float>(av[i]);
     } else {
       double v[D];
       double w[D];
@@ -341,7 +394,7 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
     const int cnt = min(SOUT, W - x_out0);
     const size_t p0 = static_cast<size_t>(y) * W + x_out0;
     stage_dwords<NWB>(reinterpret_cast<const uint32_t*>(minv + p0 * RW), stage,
-                     cnt * RW * (RIDGE ? 2 : 1), wv, lane);
+                     cnt * RW * (minv_elem_bytes(MODE) / 4), wv, lane);
   };
 
   // waves past the channel groups (wv >= NW) only stage and solve
@@ -468,16 +521,16 @@ __device__ __forceinline__ void coef_strip(const TIN* __restrict__ cost, int cos
   }
 }
 
-template <int R, int CPW, int NG, int RIDGE, typename TIN, int SIN>
+template <int R, int CPW, int NG, int MODE, typename TIN, int SIN>
 __global__ __launch_bounds__(768) void coef_kernel(
     const TIN* __restrict__ cost, int cost_ld, const float* __restrict__ g32,
     const void* __restrict__ minv, float* __restrict__ ws,
     int H, int W, int label_count, int band_h, int strips, int bands) {
   constexpr int SOUT = SIN - 2 * R;
   constexpr int NCH = NG + 1;
-  constexpr int OC = coef_column_chunk<NCH, SOUT, SIN, RIDGE>();
+  constexpr int OC = coef_column_chunk<NCH, SOUT, SIN, MODE>();
   __shared__ float lds[OC * NCH * 64];
-  __shared__ float4 stage4[coef_stage_dwords<SOUT, NG, RIDGE>() / 4];
+  __shared__ float4 stage4[coef_stage_dwords<SOUT, NG, MODE>() / 4];
   __shared__ float cbuf[2 * SIN * 64];
   __shared__ float4 gbuf4[2 * NCH * 16];
   uint32_t* stage = reinterpret_cast<uint32_t*>(stage4);
@@ -504,16 +557,16 @@ __global__ __launch_bounds__(768) void coef_kernel(
   const size_t P = static_cast<size_t>(H) * W;
   float* __restrict__ wsc = ws + static_cast<size_t>(chunk) * P * NCH * 64;
   if (xs >= 0 && xs + SIN <= W)
-    coef_strip<R, CPW, NG, RIDGE, TIN, SIN, false>(cost, cost_ld, g32, minv, wsc, H, W, xs,
+    coef_strip<R, CPW, NG, MODE, TIN, SIN, false>(cost, cost_ld, g32, minv, wsc, H, W, xs,
                                                    x_out0, y0, y1, labc, wv, lane, lds, stage,
                                                    cbuf, reinterpret_cast<float*>(gbuf4));
   else
-    coef_strip<R, CPW, NG, RIDGE, TIN, SIN, true>(cost, cost_ld, g32, minv, wsc, H, W, xs,
+    coef_strip<R, CPW, NG, MODE, TIN, SIN, true>(cost, cost_ld, g32, minv, wsc, H, W, xs,
                                                   x_out0, y0, y1, labc, wv, lane, lds, stage,
                                                    cbuf, reinterpret_cast<float*>(gbuf4));
 }
 
-template <int R, int NG, int RIDGE, typename TIN>
+template <int R, int NG, int MODE, typename TIN>
 hipError_t coef_launch_t(const CoefLaunch& a, hipStream_t s) {
   constexpr int NCH = NG + 1;
   constexpr int CPW = NCH > 10 ? 2 : 1;
@@ -521,32 +574,36 @@ hipError_t coef_launch_t(const CoefLaunch& a, hipStream_t s) {
   constexpr int SIN = coef_strip_width(NG);
   const StripGrid& g = a.grid;
   const unsigned blocks = static_cast<unsigned>(g.strips * g.bands * g.chunks);
-  hipLaunchKernelGGL((coef_kernel<R, CPW, NG, RIDGE, TIN, SIN>), dim3(blocks), dim3(NWB * 64), 0, s,
-                     static_cast<const TIN*>(a.cost), a.cost_ld, a.g32, a.minv, a.ws, a.H,
+  hipLaunchKernelGGL((coef_kernel<R, CPW, NG, MODE, TIN, SIN>), dim3(blocks), dim3(NWB * 64), 0,
+                     s, static_cast<const TIN*>(a.cost), a.cost_ld, a.g32, a.minv, a.ws, a.H,
                      a.W, a.label_count, g.band_h, g.strips, g.bands);
   return hipGetLastError();
 }
 
-template <int NG>
-hipError_t coef_launch_n(const CoefLaunch& a, hipStream_t s) {
-#define HGF_COEF_R(r)                                                        \
-  case r:                                                                    \
-    if (a.reg == 0) {                                                        \
-      if (a.cost_bf16) return coef_launch_t<r, NG, 0, uint16_t>(a, s);       \
-      return coef_launch_t<r, NG, 0, float>(a, s);                           \
-    }                                                                        \
-    if (a.cost_bf16) return hipErrorNotSupported;                            \
-    return coef_launch_t<r, NG, 1, float>(a, s);
-  switch (a.R) {
-    HGF_COEF_R(1)
-    HGF_COEF_R(2)
-    HGF_COEF_R(4)
-    HGF_COEF_R(7)
-    HGF_COEF_R(9)
-    default:
-      return hipErrorNotSupported;
+// Every solve mode and cost type of one (n, radius): the ridge form with
+// float32 costs, the covariance form with float32, bfloat16 or float16 costs
+// and a float32 or float64 solve.
+template <int NG, int R>
+hipError_t coef_launch_nr(const CoefLaunch& a, hipStream_t s) {
+  if (a.mode == kSolveRidge) {
+    if (a.cost_type != kCostF32) return hipErrorNotSupported;
+    return coef_launch_t<R, NG, kSolveRidge, float>(a, s);
   }
-#undef HGF_COEF_R
+  if (a.mode == kSolveCov64) {
+    switch (a.cost_type) {
+      case kCostF32: return coef_launch_t<R, NG, kSolveCov64, float>(a, s);
+      case kCostBF16: return coef_launch_t<R, NG, kSolveCov64, bf16_t>(a, s);
+      case kCostF16: return coef_launch_t<R, NG, kSolveCov64, f16_t>(a, s);
+      default: return hipErrorNotSupported;
+    }
+  }
+  if (a.mode != kSolveCov32) return hipErrorNotSupported;
+  switch (a.cost_type) {
+    case kCostF32: return coef_launch_t<R, NG, kSolveCov32, float>(a, s);
+    case kCostBF16: return coef_launch_t<R, NG, kSolveCov32, bf16_t>(a, s);
+    case kCostF16: return coef_launch_t<R, NG, kSolveCov32, f16_t>(a, s);
+    default: return hipErrorNotSupported;
+  }
 }
 
 }  // namespace hgf

@@ -6,65 +6,32 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
-#include <string>
 #include <vector>
 
 #include "runtime.hpp"
 
 namespace hgf {
-hipError_t launch_coef_n1(const CoefLaunch&, hipStream_t);
-hipError_t launch_coef_n2(const CoefLaunch&, hipStream_t);
-hipError_t launch_coef_n3(const CoefLaunch&, hipStream_t);
-hipError_t launch_coef_n4(const CoefLaunch&, hipStream_t);
-hipError_t launch_coef_n5(const CoefLaunch&, hipStream_t);
-hipError_t launch_coef_n6(const CoefLaunch&, hipStream_t);
-hipError_t launch_coef_n7(const CoefLaunch&, hipStream_t);
-hipError_t launch_coef_n8(const CoefLaunch&, hipStream_t);
-hipError_t launch_coef_n9(const CoefLaunch&, hipStream_t);
-hipError_t launch_coef_n19(const CoefLaunch&, hipStream_t);
-
-hipError_t launch_coef(const CoefLaunch& a, hipStream_t s) {
-  switch (a.n) {
-    case 1: return launch_coef_n1(a, s);
-    case 2: return launch_coef_n2(a, s);
-    case 3: return launch_coef_n3(a, s);
-    case 4: return launch_coef_n4(a, s);
-    case 5: return launch_coef_n5(a, s);
-    case 6: return launch_coef_n6(a, s);
-    case 7: return launch_coef_n7(a, s);
-    case 8: return launch_coef_n8(a, s);
-    case 9: return launch_coef_n9(a, s);
-    case 19: return launch_coef_n19(a, s);
-    default: return hipErrorNotSupported;
-  }
-}
-
-bool radius_supported(int R) { return R == 1 || R == 2 || R == 4 || R == 7 || R == 9; }
-
-bool config_supported(int n, int R, int reg) {
-  (void)reg;
-  const bool n_ok = (n >= 1 && n <= 9) || n == 19;
-  return n_ok && radius_supported(R);
-}
-
 // Strips of (sin - 2R) output columns, label chunks, and as many bands as fit
-// in target_blocks (never more: a grid slightly larger than a multiple of the
-// resident workgroup slots leaves a nearly empty last round).  Each band
-// restarts the vertical running sums (2R + 1 rows of set-up), so bands are at
-// least kMinBand rows; at most kMaxBand rows bound the float32 drift of the
-// running sums.
+// in target_blocks with every chunk of the volume in one launch (never more:
+// a grid slightly larger than a multiple of the resident workgroup slots
+// leaves a nearly empty last round).  Each band restarts the vertical running
+// sums (2R + 1 rows of set-up), so bands are at least kMinBand rows; at most
+// kMaxBand rows bound the float32 drift of the running sums.
 constexpr int kMinBand = 4;
 constexpr int kMaxBand = 64;
 
-StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_blocks) {
+StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int chunks_total,
+                       int target_blocks) {
   StripGrid g;
   const int sout = sin - 2 * R;
   g.strips = (W + sout - 1) / sout;
   g.chunks = chunks;
-  const int per_band = std::max(1, g.strips * chunks);
+  const int per_band = std::max(1, g.strips * chunks_total);
   const int bands = std::max(1, target_blocks / per_band);
   int band_h = (H + bands - 1) / bands;
   band_h = std::min(kMaxBand, std::max(kMinBand, band_h));
@@ -74,24 +41,29 @@ StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_bloc
 }
 
 StripGrid strip_grid(int H, int W, int R, int chunks, int target_blocks) {
-  return strip_grid_w(H, W, R, kStrip, chunks, target_blocks);
+  return strip_grid_w(H, W, R, kStrip, chunks, chunks, target_blocks);
 }
 
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
-static thread_local std::string g_last_error;
+static thread_local char g_last_error[512];
 
-hgf_status fail(hgf_status st, const std::string& msg) {
-  g_last_error = msg;
+hgf_status fail(hgf_status st, const char* fmt, ...) noexcept {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
   return st;
 }
 
-hgf_status device_fail(hipError_t e, const char* where) {
+hgf_status device_fail(hipError_t e, const char* where) noexcept {
   if (e == hipErrorNotSupported)
-    return fail(HGF_E_UNSUPPORTED, std::string(where) + ": configuration not compiled in");
-  return fail(HGF_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+    return fail(HGF_E_UNSUPPORTED, "%s: configuration not compiled in", where);
+  return fail(HGF_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
 }
+
+const char* thread_error() noexcept { return g_last_error; }
 
 // ---------------------------------------------------------------------------
 // guidance basis (Sec. 4.2)
@@ -142,8 +114,6 @@ bool build_table(int m, int d, int basis, MonoTable* t) {
 // ---------------------------------------------------------------------------
 // validation and workspace plan
 // ---------------------------------------------------------------------------
-constexpr size_t kWsCapBytes = size_t(12) << 30;  // coefficient workspace per launch group
-
 hgf_status validate(const hgf_params* p, MonoTable* table) {
   if (p == nullptr) return fail(HGF_E_INVALID, "params is NULL");
   if (p->height < 1 || p->width < 1) return fail(HGF_E_INVALID, "height and width must be >= 1");
@@ -160,18 +130,19 @@ hgf_status validate(const hgf_params* p, MonoTable* table) {
   if (p->num_labels < 1) return fail(HGF_E_INVALID, "num_labels must be >= 1");
   if (!(p->eps > 0.0) || !std::isfinite(p->eps))
     return fail(HGF_E_INVALID, "eps must be finite and > 0 (Prop. 1 divides by it)");
-  if (p->cost_dtype != HGF_F32 && p->cost_dtype != HGF_BF16)
-    return fail(HGF_E_INVALID, "cost_dtype must be HGF_F32 or HGF_BF16");
+  if (p->cost_dtype != HGF_F32 && p->cost_dtype != HGF_BF16 && p->cost_dtype != HGF_F16)
+    return fail(HGF_E_INVALID, "cost_dtype must be HGF_F32, HGF_BF16 or HGF_F16");
+  if (p->stats_dtype != HGF_F32 && p->stats_dtype != HGF_F64)
+    return fail(HGF_E_INVALID, "stats_dtype must be HGF_F32 or HGF_F64");
   if (p->cost_ld != 0 && p->cost_ld < p->num_labels)
     return fail(HGF_E_INVALID, "cost_ld must be 0 or >= num_labels");
   if (p->out_ld != 0 && p->out_ld < p->num_labels)
     return fail(HGF_E_INVALID, "out_ld must be 0 or >= num_labels");
-  if (p->reserved != 0) return fail(HGF_E_INVALID, "reserved must be 0");
   const int n = num_channels_impl(p->guide_channels, p->degree, p->basis);
   if (n < 1) return fail(HGF_E_INVALID, "invalid guide_channels/degree/basis");
-  if (!config_supported(n, p->radius, p->reg))
-    return fail(HGF_E_UNSUPPORTED, "n=" + std::to_string(n) + " radius=" +
-                                       std::to_string(p->radius) + " not compiled in");
+  if (!config_supported(n, p->radius))
+    return fail(HGF_E_UNSUPPORTED, "n=%d radius=%d not compiled in (n 1..%d, radius %d..%d)",
+                n, p->radius, kMaxN, kMinRadius, kMaxRadius);
   if (p->reg == HGF_REG_RIDGE && p->cost_dtype != HGF_F32)
     return fail(HGF_E_UNSUPPORTED, "ridge form is compiled for float32 costs only");
   if (!build_table(p->guide_channels, p->degree, p->basis, table))
@@ -179,12 +150,14 @@ hgf_status validate(const hgf_params* p, MonoTable* table) {
   return HGF_OK;
 }
 
-Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
+Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_ws, size_t group_bytes) {
   Plan pl;
   pl.table = table;
   pl.n = table.n;
   pl.reg = p->reg;
-  pl.bf16 = p->cost_dtype == HGF_BF16 ? 1 : 0;
+  pl.cost_type = p->cost_dtype;
+  pl.mode = p->reg == HGF_REG_RIDGE ? kSolveRidge
+                                    : (p->stats_dtype == HGF_F64 ? kSolveCov64 : kSolveCov32);
   pl.eps = p->eps;
   pl.D = p->reg == HGF_REG_RIDGE ? pl.n + 1 : pl.n;
   pl.PD = pl.D * (pl.D + 1) / 2;
@@ -194,10 +167,10 @@ Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
   pl.P = pl.H * pl.W;
   pl.R = p->radius;
   pl.L = p->num_labels;
-  pl.chunks_total = chunks_total;
+  pl.chunks_total = (pl.L + 63) / 64;
   pl.ws_chunk_bytes = static_cast<size_t>(pl.P) * (pl.n + 1) * 64 * sizeof(float);
-  pl.chunks_per_launch = static_cast<int>(
-      std::max<size_t>(1, std::min<size_t>(chunks_total, kWsCapBytes / pl.ws_chunk_bytes)));
+  pl.chunks_per_launch = static_cast<int>(std::max<size_t>(
+      1, std::min<size_t>(std::min(chunks_ws, pl.chunks_total), group_bytes / pl.ws_chunk_bytes)));
   size_t off = 0;
   pl.off_shift = off;
   off = align_up(off + sizeof(double) * kMaxD);
@@ -208,8 +181,8 @@ Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_total) {
   pl.off_mu = off;
   off = align_up(off + sizeof(double) * static_cast<size_t>(pl.P) * pl.n);
   pl.off_minv = off;
-  off = align_up(off + static_cast<size_t>(minv_elem_bytes(p->reg)) * pl.P *
-                           minv_stride(p->reg, pl.n));
+  off = align_up(off + static_cast<size_t>(minv_elem_bytes(pl.mode)) * pl.P *
+                           minv_stride(pl.mode, pl.n));
   pl.off_x = off;
   const size_t s_bytes = sizeof(double) * static_cast<size_t>(pl.P) * pl.K;
   const size_t ws_bytes = pl.ws_chunk_bytes * pl.chunks_per_launch;
@@ -230,7 +203,7 @@ int size_class(int P) {
 }
 
 TuneKey tune_key(int kernel, const Plan& pl) {
-  return TuneKey(kernel, pl.n, pl.R, pl.reg, pl.bf16, size_class(pl.P));
+  return TuneKey(kernel, pl.n, pl.R, pl.reg, pl.cost_type, size_class(pl.P));
 }
 
 const std::vector<int>& tune_candidates() {
@@ -261,7 +234,7 @@ hgf_status ctx_alloc(hgf_context* ctx, size_t bytes, void** out) {
   if (cur != ctx->device) (void)hipSetDevice(cur);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    return fail(HGF_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return fail(HGF_E_NOMEM, "hipMalloc of %zu bytes: %s", bytes, hipGetErrorString(e));
   }
   ctx->allocated += bytes;
   *out = p;
@@ -274,13 +247,24 @@ void ctx_free(hgf_context* ctx, void* p, size_t bytes) {
   ctx->allocated -= std::min(ctx->allocated, bytes);
 }
 
+hgf_status mark_used(hipEvent_t* ev, hipStream_t s) {
+  if (*ev == nullptr)
+    HGF_TRY(hipEventCreateWithFlags(ev, hipEventDisableTiming), "hipEventCreate");
+  HGF_TRY(hipEventRecord(*ev, s), "hipEventRecord");
+  return HGF_OK;
+}
+
+void wait_used(hipEvent_t ev) {
+  if (ev != nullptr) (void)hipEventSynchronize(ev);
+}
+
 hgf_status ctx_scratch(hgf_context* ctx, size_t bytes, void** out) {
   if (ctx->scratch_bytes >= bytes) {
     *out = ctx->scratch;
     return HGF_OK;
   }
-  // the previous scratch may still be in use by queued work on some stream
-  (void)hipDeviceSynchronize();
+  // the previous scratch may still be in use by the last call that took it
+  wait_used(ctx->scratch_used);
   ctx_free(ctx, ctx->scratch, ctx->scratch_bytes);
   ctx->scratch = nullptr;
   ctx->scratch_bytes = 0;
@@ -365,7 +349,7 @@ hgf_status run_guide(hgf_context* ctx, const Plan& pl, const float* guide, void*
   }
   {
     Stage st(ctx, 3, s);
-    HGF_TRY(launch_invert(at<double>(ws, pl.off_x), pl.n, pl.H, pl.W, pl.R, pl.eps, pl.reg,
+    HGF_TRY(launch_invert(at<double>(ws, pl.off_x), pl.n, pl.H, pl.W, pl.R, pl.eps, pl.mode,
                           at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv), s),
             "invert");
   }
@@ -377,14 +361,14 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
                       int count,
                       const float* g32, const void* minv, float* wsbuf,
                       hipStream_t s) {
-  const size_t esz = pl.bf16 ? 2 : 4;
+  const size_t esz = pl.cost_type == kCostF32 ? 4 : 2;
   if (pl.L == 1 && count == 1) {
     // a one-label filter: lanes as pixels (the label-lane kernels would idle
     // 63 lanes).  Only for filters of one label, so that a one-label chunk of
     // a larger filter takes the same kernels as the whole filter.
     SingleLaunch sa;
     sa.cost = cost;
-    sa.cost_bf16 = pl.bf16;
+    sa.cost_type = pl.cost_type;
     sa.cost_ld = cost_ld;
     sa.g32 = g32;
     sa.minv = minv;
@@ -398,7 +382,7 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
     sa.H = pl.H;
     sa.W = pl.W;
     sa.R = pl.R;
-    sa.reg = pl.reg;
+    sa.mode = pl.mode;
     Stage st(ctx, 4, s);
     HGF_TRY(launch_single(sa, s), "single-slice filter");
     return HGF_OK;
@@ -410,7 +394,7 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
     const int chunks = (lc + 63) / 64;
     CoefLaunch ca;
     ca.cost = static_cast<const char*>(cost) + esz * l0;
-    ca.cost_bf16 = pl.bf16;
+    ca.cost_type = pl.cost_type;
     ca.cost_ld = cost_ld;
     ca.g32 = g32;
     ca.minv = minv;
@@ -419,9 +403,10 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
     ca.H = pl.H;
     ca.W = pl.W;
     ca.R = pl.R;
-    ca.reg = pl.reg;
+    ca.mode = pl.mode;
     ca.label_count = lc;
-    ca.grid = strip_grid_w(pl.H, pl.W, pl.R, coef_strip_width(pl.n), chunks, coef_target);
+    ca.grid = strip_grid_w(pl.H, pl.W, pl.R, coef_strip_width(pl.n), chunks, pl.chunks_total,
+                           coef_target);
     {
       Stage st(ctx, 4, s);
       HGF_TRY(launch_coef(ca, s), "coef");
@@ -439,7 +424,7 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
     oa.W = pl.W;
     oa.R = pl.R;
     oa.label_count = lc;
-    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, out_strip_width(pl.n), chunks,
+    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, out_strip_width(pl.n), chunks, pl.chunks_total,
                            out_target);
     {
       Stage st(ctx, 5, s);
@@ -484,6 +469,19 @@ using namespace hgf;
 // ===========================================================================
 void hgf_release_batch_resources(hgf_context* ctx);  // batch.hip
 
+namespace {
+
+hgf_status check_workspace(const Plan& pl, void* ws, size_t bytes) {
+  if (bytes < pl.total)
+    return fail(HGF_E_INVALID, "workspace of %zu bytes is smaller than the %zu this call needs",
+                bytes, pl.total);
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0)
+    return fail(HGF_E_INVALID, "workspace must be 256-byte aligned");
+  return HGF_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t hgf_num_channels(int32_t m, int32_t d, int32_t basis) {
@@ -491,237 +489,280 @@ int32_t hgf_num_channels(int32_t m, int32_t d, int32_t basis) {
 }
 
 int32_t hgf_is_supported(int32_t n, int32_t radius, int32_t reg) {
-  return config_supported(n, radius, reg) ? 1 : 0;
+  return (reg == HGF_REG_COVARIANCE || reg == HGF_REG_RIDGE) && config_supported(n, radius) ? 1
+                                                                                           : 0;
 }
 
 hgf_status hgf_create(int32_t device, size_t hbm_budget_bytes, hgf_context** out) {
-  if (out == nullptr) return fail(HGF_E_INVALID, "out is NULL");
-  *out = nullptr;
-  int count = 0;
-  const hipError_t e = hipGetDeviceCount(&count);
-  if (e != hipSuccess || count == 0) return fail(HGF_E_DEVICE, "no HIP device");
-  if (device < 0 || device >= count) return fail(HGF_E_INVALID, "device index out of range");
-  hgf_context* ctx = new (std::nothrow) hgf_context();
-  if (ctx == nullptr) return fail(HGF_E_NOMEM, "host allocation");
-  ctx->device = device;
-  ctx->budget = hbm_budget_bytes;
-  *out = ctx;
-  return HGF_OK;
+  return guarded(nullptr, [&]() -> hgf_status {
+    if (out == nullptr) return fail(HGF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    const hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0) return fail(HGF_E_DEVICE, "no HIP device");
+    if (device < 0 || device >= count) return fail(HGF_E_INVALID, "device index out of range");
+    hgf_context* ctx = new (std::nothrow) hgf_context();
+    if (ctx == nullptr) return fail(HGF_E_NOMEM, "host allocation");
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    *out = ctx;
+    return HGF_OK;
+  });
 }
 
 void hgf_destroy(hgf_context* ctx) {
   if (ctx == nullptr) return;
-  (void)hipDeviceSynchronize();
-  hgf_release_batch_resources(ctx);
-  for (auto& r : ctx->recs) {
-    ctx->spare.push_back(r.start);
-    ctx->spare.push_back(r.stop);
+  try {
+    // work that still uses context-owned memory: the last call that took the
+    // scratch buffer, the last batch graph launch and the batch worker streams
+    wait_used(ctx->scratch_used);
+    wait_used(ctx->batch_done);
+    for (hipStream_t st : ctx->workers) (void)hipStreamSynchronize(st);
+    hgf_release_batch_resources(ctx);
+    for (auto& r : ctx->recs) {
+      ctx->spare.push_back(r.start);
+      ctx->spare.push_back(r.stop);
+    }
+    for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
+    if (ctx->scratch_used != nullptr) (void)hipEventDestroy(ctx->scratch_used);
+    if (ctx->batch_done != nullptr) (void)hipEventDestroy(ctx->batch_done);
+    ctx_free(ctx, ctx->scratch, ctx->scratch_bytes);
+  } catch (...) {
   }
-  for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
-  ctx_free(ctx, ctx->scratch, ctx->scratch_bytes);
   delete ctx;
 }
 
 hgf_status hgf_workspace_size(const hgf_params* params, size_t* bytes) {
-  if (bytes == nullptr) return fail(HGF_E_INVALID, "bytes is NULL");
-  MonoTable t;
-  const hgf_status st = validate(params, &t);
-  if (st != HGF_OK) return st;
-  *bytes = make_plan(params, t, (params->num_labels + 63) / 64).total;
-  return HGF_OK;
+  return guarded(nullptr, [&]() -> hgf_status {
+    if (bytes == nullptr) return fail(HGF_E_INVALID, "bytes is NULL");
+    MonoTable t;
+    const hgf_status st = validate(params, &t);
+    if (st != HGF_OK) return st;
+    *bytes = make_plan(params, t, (params->num_labels + 63) / 64).total;
+    return HGF_OK;
+  });
+}
+
+hgf_status hgf_set_group_bytes(hgf_context* ctx, size_t bytes) {
+  return guarded(ctx, [&]() -> hgf_status {
+    if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
+    ctx->group_bytes = bytes == 0 ? kDefaultGroupBytes : bytes;
+    return HGF_OK;
+  });
 }
 
 hgf_status hgf_filter(hgf_context* ctx, const hgf_params* params, const float* guide,
                       const void* cost, float* out, int32_t* labels, void* workspace,
                       size_t workspace_bytes, void* hip_stream) {
-  if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
-  MonoTable t;
-  hgf_status st = validate(params, &t);
-  if (st != HGF_OK) return st;
-  if (guide == nullptr || cost == nullptr) return fail(HGF_E_INVALID, "guide or cost is NULL");
-  if (out == nullptr && labels == nullptr)
-    return fail(HGF_E_INVALID, "out and labels are both NULL: nothing to compute");
-  const Plan pl = make_plan(params, t, (params->num_labels + 63) / 64);
-  void* ws = workspace;
-  if (ws == nullptr) {
-    st = ctx_scratch(ctx, pl.total, &ws);
+  return guarded(ctx, [&]() -> hgf_status {
+    if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
+    MonoTable t;
+    hgf_status st = validate(params, &t);
     if (st != HGF_OK) return st;
-  } else {
-    if (workspace_bytes < pl.total)
-      return fail(HGF_E_INVALID, "workspace smaller than hgf_workspace_size()");
-    if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0)
-      return fail(HGF_E_INVALID, "workspace must be 256-byte aligned");
-  }
-  const int cost_ld = params->cost_ld ? params->cost_ld : params->num_labels;
-  const int out_ld = params->out_ld ? params->out_ld : params->num_labels;
-  return run_filter(ctx, pl, guide, cost, cost_ld, out, out_ld, labels, ws,
-                    static_cast<hipStream_t>(hip_stream));
+    if (guide == nullptr || cost == nullptr) return fail(HGF_E_INVALID, "guide or cost is NULL");
+    if (out == nullptr && labels == nullptr)
+      return fail(HGF_E_INVALID, "out and labels are both NULL: nothing to compute");
+    const Plan pl = make_plan(params, t, (params->num_labels + 63) / 64, ctx->group_bytes);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    void* ws = workspace;
+    if (ws == nullptr) {
+      st = ctx_scratch(ctx, pl.total, &ws);
+      if (st != HGF_OK) return st;
+    } else {
+      st = check_workspace(pl, ws, workspace_bytes);
+      if (st != HGF_OK) return st;
+    }
+    const int cost_ld = params->cost_ld ? params->cost_ld : params->num_labels;
+    const int out_ld = params->out_ld ? params->out_ld : params->num_labels;
+    st = run_filter(ctx, pl, guide, cost, cost_ld, out, out_ld, labels, ws, s);
+    if (workspace == nullptr) {
+      const hgf_status m = mark_used(&ctx->scratch_used, s);
+      if (st == HGF_OK) st = m;
+    }
+    return st;
+  });
 }
 
 hgf_status hgf_guide_create(hgf_context* ctx, const hgf_params* params, const float* guide,
                             void* hip_stream, hgf_guide** out) {
-  if (ctx == nullptr || out == nullptr) return fail(HGF_E_INVALID, "context or out is NULL");
-  *out = nullptr;
-  MonoTable t;
-  hgf_status st = validate(params, &t);
-  if (st != HGF_OK) return st;
-  if (guide == nullptr) return fail(HGF_E_INVALID, "guide is NULL");
-  hgf_guide* g = new (std::nothrow) hgf_guide();
-  if (g == nullptr) return fail(HGF_E_NOMEM, "host allocation");
-  g->ctx = ctx;
-  g->params = *params;
-  // label chunks per hgf_guide_filter launch group: one chunk of 64
-  g->plan = make_plan(params, t, 1);
-  g->bytes = g->plan.total;
-  st = ctx_alloc(ctx, g->bytes, &g->base);
-  if (st != HGF_OK) {
-    delete g;
-    return st;
-  }
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  st = run_guide(ctx, g->plan, guide, g->base, s);
-  if (st != HGF_OK) {
-    (void)hipStreamSynchronize(s);
-    ctx_free(ctx, g->base, g->bytes);
-    delete g;
-    return st;
-  }
-  *out = g;
-  return HGF_OK;
+  return guarded(ctx, [&]() -> hgf_status {
+    if (ctx == nullptr || out == nullptr) return fail(HGF_E_INVALID, "context or out is NULL");
+    *out = nullptr;
+    MonoTable t;
+    hgf_status st = validate(params, &t);
+    if (st != HGF_OK) return st;
+    if (guide == nullptr) return fail(HGF_E_INVALID, "guide is NULL");
+    hgf_guide* g = new (std::nothrow) hgf_guide();
+    if (g == nullptr) return fail(HGF_E_NOMEM, "host allocation");
+    g->ctx = ctx;
+    g->params = *params;
+    // coefficient workspace for one chunk of 64 labels: a filter call runs
+    // its chunks one launch group after another
+    g->plan = make_plan(params, t, 1, ctx->group_bytes);
+    g->bytes = g->plan.total;
+    st = ctx_alloc(ctx, g->bytes, &g->base);
+    if (st != HGF_OK) {
+      delete g;
+      return st;
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    st = run_guide(ctx, g->plan, guide, g->base, s);
+    if (st == HGF_OK) st = mark_used(&g->used, s);
+    if (st != HGF_OK) {
+      (void)hipStreamSynchronize(s);
+      ctx_free(ctx, g->base, g->bytes);
+      if (g->used != nullptr) (void)hipEventDestroy(g->used);
+      delete g;
+      return st;
+    }
+    *out = g;
+    return HGF_OK;
+  });
 }
 
 hgf_status hgf_guide_filter(hgf_context* ctx, hgf_guide* g, const void* cost_chunk,
                             int32_t label_begin, int32_t label_count, int32_t ld,
                             float* out_chunk, float* best_cost, int32_t* labels,
                             void* hip_stream) {
-  if (ctx == nullptr || g == nullptr) return fail(HGF_E_INVALID, "context or guide is NULL");
-  if (cost_chunk == nullptr) return fail(HGF_E_INVALID, "cost_chunk is NULL");
-  if (label_count < 1 || label_begin < 0 ||
-      static_cast<int64_t>(label_begin) + label_count > g->params.num_labels)
-    return fail(HGF_E_INVALID, "label range outside [0, num_labels)");
-  if (ld != 0 && ld < label_count) return fail(HGF_E_INVALID, "ld must be 0 or >= label_count");
-  if ((best_cost == nullptr) != (labels == nullptr))
-    return fail(HGF_E_INVALID, "best_cost and labels must both be given or both be NULL");
-  if (out_chunk == nullptr && labels == nullptr)
-    return fail(HGF_E_INVALID, "out_chunk and labels are both NULL: nothing to compute");
-  const Plan& pl = g->plan;
-  const int ldv = ld ? ld : label_count;
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  void* base = g->base;
-  unsigned long long* keys = labels != nullptr ? at<unsigned long long>(base, pl.off_keys) : nullptr;
-  if (keys != nullptr) {
-    Stage sk(ctx, 6, s);
-    HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
-  }
-  const hgf_status st = run_labels(ctx, pl, cost_chunk, ldv, out_chunk, ldv, keys, nullptr,
-                                   label_begin,
-                                   label_count, pl.g32(base),
-                                   at<char>(base, pl.off_minv), at<float>(base, pl.off_x), s);
-  if (st != HGF_OK) return st;
-  if (keys != nullptr) {
-    Stage sk(ctx, 6, s);
-    HGF_TRY(launch_key_finalize(keys, pl.P, best_cost, labels, label_begin > 0 ? 1 : 0, s),
-            "key_finalize");
-  }
-  return HGF_OK;
+  return guarded(ctx, [&]() -> hgf_status {
+    if (ctx == nullptr || g == nullptr) return fail(HGF_E_INVALID, "context or guide is NULL");
+    if (cost_chunk == nullptr) return fail(HGF_E_INVALID, "cost_chunk is NULL");
+    if (label_count < 1 || label_begin < 0 ||
+        static_cast<int64_t>(label_begin) + label_count > g->params.num_labels)
+      return fail(HGF_E_INVALID, "label range outside [0, num_labels)");
+    if (ld != 0 && ld < label_count) return fail(HGF_E_INVALID, "ld must be 0 or >= label_count");
+    if ((best_cost == nullptr) != (labels == nullptr))
+      return fail(HGF_E_INVALID, "best_cost and labels must both be given or both be NULL");
+    if (out_chunk == nullptr && labels == nullptr)
+      return fail(HGF_E_INVALID, "out_chunk and labels are both NULL: nothing to compute");
+    const Plan& pl = g->plan;
+    const int ldv = ld ? ld : label_count;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    void* base = g->base;
+    unsigned long long* keys =
+        labels != nullptr ? at<unsigned long long>(base, pl.off_keys) : nullptr;
+    if (keys != nullptr) {
+      Stage sk(ctx, 6, s);
+      HGF_TRY(launch_key_fill(keys, pl.P, s), "key_fill");
+    }
+    hgf_status st = run_labels(ctx, pl, cost_chunk, ldv, out_chunk, ldv, keys, nullptr,
+                               label_begin, label_count, pl.g32(base),
+                               at<char>(base, pl.off_minv), at<float>(base, pl.off_x), s);
+    if (st == HGF_OK && keys != nullptr) {
+      Stage sk(ctx, 6, s);
+      HGF_TRY(launch_key_finalize(keys, pl.P, best_cost, labels, label_begin > 0 ? 1 : 0, s),
+              "key_finalize");
+    }
+    const hgf_status m = mark_used(&g->used, s);
+    return st != HGF_OK ? st : m;
+  });
 }
 
 size_t hgf_guide_bytes(const hgf_guide* g) { return g != nullptr ? g->bytes : 0; }
 
 void hgf_guide_destroy(hgf_guide* g) {
   if (g == nullptr) return;
-  (void)hipDeviceSynchronize();
-  if (g->owns) ctx_free(g->ctx, g->base, g->bytes);
+  try {
+    // only the work that used this guide's buffer, not the whole device
+    wait_used(g->used);
+    if (g->used != nullptr) (void)hipEventDestroy(g->used);
+    if (g->owns) ctx_free(g->ctx, g->base, g->bytes);
+  } catch (...) {
+  }
   delete g;
 }
 
 hgf_status hgf_guide_export(const hgf_guide* g, double* mu, void* minv, double* shift,
                             void* hip_stream) {
-  if (g == nullptr) return fail(HGF_E_INVALID, "guide is NULL");
-  const Plan& pl = g->plan;
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (mu != nullptr)
-    HGF_TRY(hipMemcpyAsync(mu, at<char>(g->base, pl.off_mu),
-                           sizeof(double) * static_cast<size_t>(pl.P) * pl.n,
-                           hipMemcpyDeviceToDevice, s),
-            "export mu");
-  if (minv != nullptr) {
-    // the packed triangle of each pixel, out of its stored record
-    const size_t eb = static_cast<size_t>(minv_elem_bytes(g->params.reg));
-    const size_t skip = g->params.reg == 0 ? static_cast<size_t>(pl.n) : 0;
-    HGF_TRY(hipMemcpy2DAsync(minv, eb * pl.PD, at<char>(g->base, pl.off_minv) + eb * skip,
-                             eb * minv_stride(g->params.reg, pl.n), eb * pl.PD,
-                             static_cast<size_t>(pl.P), hipMemcpyDeviceToDevice, s),
-            "export minv");
-  }
-  if (shift != nullptr)
-    HGF_TRY(hipMemcpyAsync(shift, at<char>(g->base, pl.off_shift), sizeof(double) * pl.n,
-                           hipMemcpyDeviceToDevice, s),
-            "export shift");
-  return HGF_OK;
+  return guarded(g != nullptr ? g->ctx : nullptr, [&]() -> hgf_status {
+    if (g == nullptr) return fail(HGF_E_INVALID, "guide is NULL");
+    const Plan& pl = g->plan;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (mu != nullptr)
+      HGF_TRY(hipMemcpyAsync(mu, at<char>(g->base, pl.off_mu),
+                             sizeof(double) * static_cast<size_t>(pl.P) * pl.n,
+                             hipMemcpyDeviceToDevice, s),
+              "export mu");
+    if (minv != nullptr) {
+      // the packed triangle of each pixel, out of its stored record
+      const size_t eb = static_cast<size_t>(minv_elem_bytes(pl.mode));
+      const size_t skip = pl.mode == kSolveRidge ? 0 : static_cast<size_t>(pl.n);
+      HGF_TRY(hipMemcpy2DAsync(minv, eb * pl.PD, at<char>(g->base, pl.off_minv) + eb * skip,
+                               eb * minv_stride(pl.mode, pl.n), eb * pl.PD,
+                               static_cast<size_t>(pl.P), hipMemcpyDeviceToDevice, s),
+              "export minv");
+    }
+    if (shift != nullptr)
+      HGF_TRY(hipMemcpyAsync(shift, at<char>(g->base, pl.off_shift), sizeof(double) * pl.n,
+                             hipMemcpyDeviceToDevice, s),
+              "export shift");
+    return HGF_OK;
+  });
 }
 
 hgf_status hgf_box_sum(const float* in, float* out, int32_t channels, int32_t height,
                        int32_t width, int32_t radius, void* hip_stream) {
-  if (in == nullptr || out == nullptr) return fail(HGF_E_INVALID, "in or out is NULL");
-  if (channels < 1 || height < 1 || width < 1 || radius < 0)
-    return fail(HGF_E_INVALID, "channels, height, width must be >= 1 and radius >= 0");
-  if (in == out) return fail(HGF_E_INVALID, "in and out must not overlap");
-  // the vertical pass writes a temporary image stack that the horizontal pass reads
-  const size_t bytes = sizeof(float) * static_cast<size_t>(channels) * height * width;
-  void* tmp = nullptr;
-  if (hipMalloc(&tmp, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(HGF_E_NOMEM, "hipMalloc for the box-sum temporary");
-  }
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  const hipError_t e = launch_box_sum(in, out, channels, height, width, radius,
-                                      static_cast<float*>(tmp), s);
-  (void)hipStreamSynchronize(s);
-  (void)hipFree(tmp);
-  if (e != hipSuccess) return device_fail(e, "box_sum");
-  return HGF_OK;
+  return guarded(nullptr, [&]() -> hgf_status {
+    if (in == nullptr || out == nullptr) return fail(HGF_E_INVALID, "in or out is NULL");
+    if (channels < 1 || height < 1 || width < 1 || radius < 0)
+      return fail(HGF_E_INVALID, "channels, height, width must be >= 1 and radius >= 0");
+    if (radius > kBoxMaxRadius) return fail(HGF_E_UNSUPPORTED, "radius above %d", kBoxMaxRadius);
+    const size_t bytes = sizeof(float) * static_cast<size_t>(channels) * height * width;
+    const char* a = reinterpret_cast<const char*>(in);
+    const char* b = reinterpret_cast<const char*>(out);
+    if (a < b + bytes && b < a + bytes) return fail(HGF_E_INVALID, "in and out must not overlap");
+    HGF_TRY(launch_box_sum(in, out, channels, height, width, radius,
+                           static_cast<hipStream_t>(hip_stream)),
+            "box_sum");
+    return HGF_OK;
+  });
 }
 
 hgf_status hgf_spd_inverse(const double* a, double* minv, int32_t dim, int32_t count,
                            void* hip_stream) {
-  if (a == nullptr || minv == nullptr) return fail(HGF_E_INVALID, "a or minv is NULL");
-  if (dim < 1 || dim > kMaxD) return fail(HGF_E_INVALID, "dim must be in [1, 20]");
-  if (count < 0) return fail(HGF_E_INVALID, "count < 0");
-  if (count == 0) return HGF_OK;
-  HGF_TRY(launch_spd_inverse(a, minv, dim, count, static_cast<hipStream_t>(hip_stream)),
-          "spd_inverse");
-  return HGF_OK;
+  return guarded(nullptr, [&]() -> hgf_status {
+    if (a == nullptr || minv == nullptr) return fail(HGF_E_INVALID, "a or minv is NULL");
+    if (dim < 1 || dim > kMaxD) return fail(HGF_E_INVALID, "dim must be in [1, 20]");
+    if (count < 0) return fail(HGF_E_INVALID, "count < 0");
+    if (count == 0) return HGF_OK;
+    HGF_TRY(launch_spd_inverse(a, minv, dim, count, static_cast<hipStream_t>(hip_stream)),
+            "spd_inverse");
+    return HGF_OK;
+  });
 }
 
 hgf_status hgf_set_stage_timing(hgf_context* ctx, int32_t enable) {
-  if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
-  ctx->timing = enable != 0;
-  return HGF_OK;
+  return guarded(ctx, [&]() -> hgf_status {
+    if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
+    ctx->timing = enable != 0;
+    return HGF_OK;
+  });
 }
 
 hgf_status hgf_stage_times(hgf_context* ctx, double* ms, int32_t* launches, int32_t max_stages) {
-  if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
-  if (max_stages < 0) return fail(HGF_E_INVALID, "max_stages < 0");
-  for (int i = 0; i < max_stages; ++i) {
-    if (ms != nullptr) ms[i] = 0.0;
-    if (launches != nullptr) launches[i] = 0;
-  }
-  hgf_status st = HGF_OK;
-  for (auto& r : ctx->recs) {
-    float t = 0.f;
-    if (hipEventSynchronize(r.stop) != hipSuccess ||
-        hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess)
-      st = fail(HGF_E_DEVICE, "stage event timing");
-    if (r.stage < max_stages) {
-      if (ms != nullptr) ms[r.stage] += t;
-      if (launches != nullptr) launches[r.stage] += 1;
+  return guarded(ctx, [&]() -> hgf_status {
+    if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
+    if (max_stages < 0) return fail(HGF_E_INVALID, "max_stages < 0");
+    for (int i = 0; i < max_stages; ++i) {
+      if (ms != nullptr) ms[i] = 0.0;
+      if (launches != nullptr) launches[i] = 0;
     }
-    ctx->spare.push_back(r.start);
-    ctx->spare.push_back(r.stop);
-  }
-  ctx->recs.clear();
-  return st;
+    hgf_status st = HGF_OK;
+    for (auto& r : ctx->recs) {
+      float t = 0.f;
+      if (hipEventSynchronize(r.stop) != hipSuccess ||
+          hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess)
+        st = fail(HGF_E_DEVICE, "stage event timing");
+      if (r.stage < max_stages) {
+        if (ms != nullptr) ms[r.stage] += t;
+        if (launches != nullptr) launches[r.stage] += 1;
+      }
+      ctx->spare.push_back(r.start);
+      ctx->spare.push_back(r.stop);
+    }
+    ctx->recs.clear();
+    return st;
+  });
 }
 
 const char* hgf_status_string(hgf_status status) {
@@ -736,6 +777,8 @@ const char* hgf_status_string(hgf_status status) {
   return "unknown hgf_status";
 }
 
-const char* hgf_last_error(void) { return g_last_error.c_str(); }
+const char* hgf_last_error(const hgf_context* ctx) {
+  return ctx != nullptr ? ctx->err : thread_error();
+}
 
 }  // extern "C"

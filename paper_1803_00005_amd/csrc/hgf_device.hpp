@@ -58,17 +58,29 @@ __device__ __forceinline__ float bf16_to_float(uint16_t b) {
   return __uint_as_float(static_cast<uint32_t>(b) << 16);
 }
 
-template <typename T>
-__device__ __forceinline__ float load_cost(const T* p, size_t i);
+// Cost element types: float32, bfloat16 (kept as its raw bits) and float16.
+struct bf16_t {
+  uint16_t bits;
+};
+using f16_t = _Float16;
 
-template <>
-__device__ __forceinline__ float load_cost<float>(const float* p, size_t i) {
-  return p[i];
+// A cost element as float32 (exact for every type).
+__device__ __forceinline__ float cost_to_float(float v) { return v; }
+__device__ __forceinline__ float cost_to_float(bf16_t v) { return bf16_to_float(v.bits); }
+__device__ __forceinline__ float cost_to_float(f16_t v) { return static_cast<float>(v); }
+
+// The float32 value of a 16-bit cost element given by its bits.
+template <typename T>
+__device__ __forceinline__ float cost_bits_to_float(uint16_t b) {
+  if constexpr (std::is_same<T, f16_t>::value)
+    return static_cast<float>(__builtin_bit_cast(f16_t, b));
+  else
+    return bf16_to_float(b);
 }
 
-template <>
-__device__ __forceinline__ float load_cost<uint16_t>(const uint16_t* p, size_t i) {
-  return bf16_to_float(p[i]);
+template <typename T>
+__device__ __forceinline__ float load_cost(const T* p, size_t i) {
+  return cost_to_float(p[i]);
 }
 
 // Order-preserving map of a float to uint32 (NaN canonicalised to +qNaN, which

@@ -8,7 +8,7 @@
 
 namespace hgf {
 
-// Per-launch geometry of a strip kernel: strips of (64 - 2R) output columns,
+// Per-launch geometry of a strip kernel: strips of (sin - 2R) output columns,
 // bands of band_h output rows, label chunks of 64 lanes.
 struct StripGrid {
   int strips;
@@ -17,8 +17,14 @@ struct StripGrid {
   int chunks;
 };
 
+// The band partition depends on the image, the strip width, the target block
+// count and the label chunk count of the whole volume (chunks_total), never
+// on how many of those chunks one launch takes (chunks): the float32 running
+// sums restart at band boundaries, so this keeps the results independent of
+// label chunking and launch groups.
 StripGrid strip_grid(int H, int W, int R, int chunks, int target_blocks);
-StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int target_blocks);
+StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int chunks_total,
+                       int target_blocks);
 
 // State columns per strip of the coefficient kernel: up to n = 9 one channel
 // per wave and 64 columns; above, two channels per wave and a narrower strip
@@ -31,8 +37,8 @@ constexpr int out_strip_width(int n) { return out_channels_per_wave(n) > 1 ? 48 
 
 // Radii with compiled strip kernels.
 bool radius_supported(int R);
-// (n, R, reg) has compiled coefficient / output / inverse kernels.
-bool config_supported(int n, int R, int reg);
+// (n, R) has compiled kernels (every solve mode and cost type).
+bool config_supported(int n, int R);
 
 // a1 + shift: guidance channel shifts (covariance form: each channel's mean
 // over a fixed grid of at most 16 x 16 pixels, an exact reformulation since
@@ -52,27 +58,42 @@ hipError_t launch_moments(const double* g64, int n, int H, int W, int R,
                           int target_blocks, double* S, hipStream_t s);
 // a3: per-pixel window mean mu [P][n] (float64, covariance form) and the
 // per-pixel inverse by the bordering recursion of Prop. 1, computed in
-// float64.  Covariance form: a float32 solve record per pixel (below); ridge
-// form: the packed upper triangle [P][D(D+1)/2] in float64.
+// float64 and stored as the solve mode says (SolveMode below).
 hipError_t launch_invert(const double* S, int n, int H, int W, int R, double eps,
-                         int reg, double* mu, void* minv, hipStream_t s);
+                         int mode, double* mu, void* minv, hipStream_t s);
 
-// Bytes per stored inverse element.
-constexpr int minv_elem_bytes(int reg) { return reg == 0 ? 4 : 8; }
+// How the per-pixel inverse is stored and applied (the solve mode):
+//   kSolveCov32  covariance form, float32 solve record per pixel: the window
+//                mean mu_1..mu_n, then the packed upper triangle of M_p
+//                (n(n+1)/2 entries, row by row), zero-padded to a multiple of
+//                four floats (16-byte reads);
+//   kSolveCov64  covariance form, the same record in float64, padded to an
+//                even number of doubles;
+//   kSolveRidge  ridge form, the packed upper triangle of the (n+1) x (n+1)
+//                inverse in float64.
+// M_p is computed in float64 in every mode.
+enum SolveMode { kSolveCov32 = 0, kSolveCov64 = 1, kSolveRidge = 2 };
 
-// Covariance-form solve record of one pixel, float32: the window mean
-// mu_1..mu_n, then the packed upper triangle of M_p (n(n+1)/2 entries, row by
-// row), zero-padded to a multiple of four floats so that the record can be
-// read with 16-byte loads.
 __host__ __device__ constexpr int cov_record_floats(int n) {
   return (n + n * (n + 1) / 2 + 3) / 4 * 4;
 }
-
-// Elements per pixel of the stored inverse: the covariance record, or the
-// packed float64 triangle of the ridge form.
-__host__ __device__ constexpr int minv_stride(int reg, int n) {
-  return reg == 0 ? cov_record_floats(n) : (n + 1) * (n + 2) / 2;
+__host__ __device__ constexpr int cov_record_doubles(int n) {
+  return (n + n * (n + 1) / 2 + 1) / 2 * 2;
 }
+
+// Elements per pixel of the stored inverse, and bytes per element.
+__host__ __device__ constexpr int minv_stride(int mode, int n) {
+  return mode == kSolveCov32 ? cov_record_floats(n)
+                             : (mode == kSolveCov64 ? cov_record_doubles(n) : (n + 1) * (n + 2) / 2);
+}
+__host__ __device__ constexpr int minv_elem_bytes(int mode) { return mode == kSolveCov32 ? 4 : 8; }
+
+// Cost element codes (hgf_dtype values of the cost volume).
+enum CostType { kCostF32 = 0, kCostBF16 = 1, kCostF16 = 2 };
+
+// Compiled set of the strip kernels.
+constexpr int kMinRadius = 0;
+constexpr int kMaxRadius = 9;
 
 // Logical block index of hardware block `bid` of `nb`: consecutive hardware
 // blocks are dispatched round-robin over the 8 XCDs, so this hands each XCD a
@@ -87,12 +108,12 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 
 struct CoefLaunch {
   const void* cost;     // [H][W][cost_ld]
-  int cost_bf16;
+  int cost_type;        // CostType
   int cost_ld;
   const float* g32;     // planar [n+1][P], channel 0 = 1, padded
-  const void* minv;     // [P][PD] float32 (covariance) or float64 (ridge)
+  const void* minv;     // [P][minv_stride(mode, n)] solve records
   float* ws;            // [chunks][P][n+1][64]
-  int n, H, W, R, reg;
+  int n, H, W, R, mode;
   int label_count;      // labels in this launch (chunks = ceil(label_count / 64))
   StripGrid grid;
 };
@@ -113,33 +134,23 @@ struct OutLaunch {
 };
 // a6 + a7: coefficient box filter, output and winner-takes-all keys.
 hipError_t launch_out(const OutLaunch& a, hipStream_t s);
-hipError_t launch_out_n1(const OutLaunch& a, hipStream_t s);
-hipError_t launch_out_n2(const OutLaunch& a, hipStream_t s);
-hipError_t launch_out_n3(const OutLaunch& a, hipStream_t s);
-hipError_t launch_out_n4(const OutLaunch& a, hipStream_t s);
-hipError_t launch_out_n5(const OutLaunch& a, hipStream_t s);
-hipError_t launch_out_n6(const OutLaunch& a, hipStream_t s);
-hipError_t launch_out_n7(const OutLaunch& a, hipStream_t s);
-hipError_t launch_out_n8(const OutLaunch& a, hipStream_t s);
-hipError_t launch_out_n9(const OutLaunch& a, hipStream_t s);
-hipError_t launch_out_n19(const OutLaunch& a, hipStream_t s);
 
 // a4 - a7 for a single label slice (L = 1) with lanes as pixels: separable
 // box sums over planar images in the workspace, which needs room for
 // 2 (n + 1) float32 images of P pixels.
 struct SingleLaunch {
   const void* cost;     // [H][W][cost_ld], the label at offset 0
-  int cost_bf16;
+  int cost_type;        // CostType
   int cost_ld;
   const float* g32;     // planar [n+1][P], channel 0 = 1, padded
-  const void* minv;     // covariance records or ridge packed inverses
+  const void* minv;     // solve records of the solve mode
   float* ws;            // >= 2 (n+1) P floats
   float* out;           // [H][W][out_ld] or null
   int out_ld;
   unsigned long long* keys;  // [P] or null
   int32_t* labels;      // [P] or null: final labels (the slice is the only label)
   int label;            // absolute label of the slice
-  int n, H, W, R, reg;
+  int n, H, W, R, mode;
 };
 hipError_t launch_single(const SingleLaunch& a, hipStream_t s);
 
@@ -151,8 +162,10 @@ hipError_t launch_key_finalize(const unsigned long long* keys, size_t count,
                                float* best, int32_t* labels, int merge,
                                hipStream_t s);
 
+// Clipped box sum of C planar float32 images (radius up to 95), in one kernel.
+constexpr int kBoxMaxRadius = 95;
 hipError_t launch_box_sum(const float* in, float* out, int C, int H, int W, int R,
-                          float* tmp, hipStream_t s);
+                          hipStream_t s);
 hipError_t launch_spd_inverse(const double* a, double* minv, int D, int count,
                               hipStream_t s);
 

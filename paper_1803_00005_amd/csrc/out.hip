@@ -1,6 +1,6 @@
-// Winner-takes-all key handling, the standalone box sum and the dispatch of
-// the output kernels (a6 + a7) over the compiled channel counts.  The output
-// kernel itself is in out.hpp, instantiated per channel count in out_n*.hip.
+// Winner-takes-all key handling and the standalone box sum.  The output
+// kernel (a6 + a7) is in out.hpp, instantiated per channel count in
+// generated units and dispatched from dispatch.hip.
 #include "hgf_launch.hpp"
 
 namespace hgf {
@@ -28,59 +28,52 @@ __global__ __launch_bounds__(256) void key_finalize_kernel(
   if (labels != nullptr) labels[i] = static_cast<int32_t>(key & 0xffffffffu);
 }
 
-// Standalone box sum: vertical running sums per (channel, column), then a
-// horizontal window sum per pixel read from the vertical result.
-__global__ __launch_bounds__(256) void box_vertical_kernel(const float* __restrict__ in,
-                                                           float* __restrict__ tmp, int C, int H,
-                                                           int W, int R) {
-  const int idx = static_cast<int>(blockIdx.x) * 256 + threadIdx.x;
-  if (idx >= C * W) return;
-  const int c = idx / W;
-  const int x = idx - c * W;
-  const float* src = in + static_cast<size_t>(c) * H * W + x;
-  float* dst = tmp + static_cast<size_t>(c) * H * W + x;
-  float s = 0.f;
-  for (int y = 0; y <= min(R, H - 1); ++y) s += src[static_cast<size_t>(y) * W];
-  for (int y = 0; y < H; ++y) {
-    if (y > 0) {
-      if (y + R < H) s += src[static_cast<size_t>(y + R) * W];
-      if (y - R - 1 >= 0) s -= src[static_cast<size_t>(y - R - 1) * W];
-    }
-    dst[static_cast<size_t>(y) * W] = s;
-  }
-}
+// Standalone box sum in one pass, no temporary: a block takes 64 output
+// columns of one channel over a band of rows; its threads keep the vertical
+// running sums of the 64 + 2R state columns (float32: exact for the integer
+// test images, whose sums stay below 2^24), publish them in LDS each row, and
+// the first 64 threads sum 2R + 1 neighbours for their output column.
+constexpr int kBoxCols = 64;
+constexpr int kBoxBand = 64;
+constexpr int kBoxThreads = 256;  // 64 output columns plus 2R state columns, R <= 95
 
-__global__ __launch_bounds__(256) void box_horizontal_kernel(const float* __restrict__ tmp,
-                                                             float* __restrict__ out, int C,
-                                                             int H, int W, int R) {
-  const size_t idx = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
-  const size_t total = static_cast<size_t>(C) * H * W;
-  if (idx >= total) return;
-  const size_t row = idx / W;
-  const int x = static_cast<int>(idx - row * W);
-  const float* src = tmp + row * W;
-  float s = 0.f;
-  for (int xx = max(0, x - R); xx <= min(W - 1, x + R); ++xx) s += src[xx];
-  out[idx] = s;
+__global__ __launch_bounds__(kBoxThreads) void box_sum_kernel(const float* __restrict__ in,
+                                                              float* __restrict__ out, int H,
+                                                              int W, int R) {
+  __shared__ float vrow[kBoxThreads];
+  const int strip = static_cast<int>(blockIdx.x);
+  const int band = static_cast<int>(blockIdx.y);
+  const int c = static_cast<int>(blockIdx.z);
+  const int t = static_cast<int>(threadIdx.x);
+  const int x0 = strip * kBoxCols;
+  const int xs = x0 - R + t;  // this thread's state column
+  const bool state = t < kBoxCols + 2 * R && xs >= 0 && xs < W;
+  const int y0 = band * kBoxBand;
+  const int y1 = min(H, y0 + kBoxBand);
+  const float* __restrict__ src = in + static_cast<size_t>(c) * H * W;
+  float* __restrict__ dst = out + static_cast<size_t>(c) * H * W;
+  float v = 0.f;
+  if (state)
+    for (int y = max(0, y0 - R); y <= min(H - 1, y0 + R); ++y)
+      v += src[static_cast<size_t>(y) * W + xs];
+  for (int y = y0; y < y1; ++y) {
+    if (y > y0 && state) {
+      if (y + R < H) v += src[static_cast<size_t>(y + R) * W + xs];
+      if (y - R - 1 >= 0) v -= src[static_cast<size_t>(y - R - 1) * W + xs];
+    }
+    vrow[t] = state ? v : 0.f;
+    __syncthreads();
+    const int x = x0 + t;
+    if (t < kBoxCols && x < W) {
+      float h = 0.f;
+      for (int k = 0; k <= 2 * R; ++k) h += vrow[t + k];
+      dst[static_cast<size_t>(y) * W + x] = h;
+    }
+    __syncthreads();
+  }
 }
 
 }  // namespace
-
-hipError_t launch_out(const OutLaunch& a, hipStream_t s) {
-  switch (a.n) {
-    case 1: return launch_out_n1(a, s);
-    case 2: return launch_out_n2(a, s);
-    case 3: return launch_out_n3(a, s);
-    case 4: return launch_out_n4(a, s);
-    case 5: return launch_out_n5(a, s);
-    case 6: return launch_out_n6(a, s);
-    case 7: return launch_out_n7(a, s);
-    case 8: return launch_out_n8(a, s);
-    case 9: return launch_out_n9(a, s);
-    case 19: return launch_out_n19(a, s);
-    default: return hipErrorNotSupported;
-  }
-}
 
 hipError_t launch_key_fill(unsigned long long* keys, size_t count, hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>((count + 255) / 256);
@@ -96,13 +89,12 @@ hipError_t launch_key_finalize(const unsigned long long* keys, size_t count, flo
   return hipGetLastError();
 }
 
-hipError_t launch_box_sum(const float* in, float* out, int C, int H, int W, int R, float* tmp,
+hipError_t launch_box_sum(const float* in, float* out, int C, int H, int W, int R,
                           hipStream_t s) {
-  const unsigned b1 = static_cast<unsigned>((C * W + 255) / 256);
-  hipLaunchKernelGGL(box_vertical_kernel, dim3(b1), dim3(256), 0, s, in, tmp, C, H, W, R);
-  const size_t total = static_cast<size_t>(C) * H * W;
-  const unsigned b2 = static_cast<unsigned>((total + 255) / 256);
-  hipLaunchKernelGGL(box_horizontal_kernel, dim3(b2), dim3(256), 0, s, tmp, out, C, H, W, R);
+  if (kBoxCols + 2 * R > kBoxThreads) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((W + kBoxCols - 1) / kBoxCols),
+                  static_cast<unsigned>((H + kBoxBand - 1) / kBoxBand), static_cast<unsigned>(C));
+  hipLaunchKernelGGL(box_sum_kernel, grid, dim3(kBoxThreads), 0, s, in, out, H, W, R);
   return hipGetLastError();
 }
 

@@ -297,13 +297,20 @@ hipError_t out_launch_t(const OutLaunch& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Every compiled radius of one channel count.
 template <int NG>
 hipError_t out_launch_n(const OutLaunch& a, hipStream_t s) {
+  static_assert(kMinRadius == 0 && kMaxRadius == 9, "the radius list below");
   switch (a.R) {
+    case 0: return out_launch_t<0, NG>(a, s);
     case 1: return out_launch_t<1, NG>(a, s);
     case 2: return out_launch_t<2, NG>(a, s);
+    case 3: return out_launch_t<3, NG>(a, s);
     case 4: return out_launch_t<4, NG>(a, s);
+    case 5: return out_launch_t<5, NG>(a, s);
+    case 6: return out_launch_t<6, NG>(a, s);
     case 7: return out_launch_t<7, NG>(a, s);
+    case 8: return out_launch_t<8, NG>(a, s);
     case 9: return out_launch_t<9, NG>(a, s);
     default: return hipErrorNotSupported;
   }

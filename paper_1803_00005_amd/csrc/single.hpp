@@ -12,10 +12,16 @@
 //   4. horizontal window sums (float64) and Z = sum_ch B(w_ch) G_ch / N (Eq. 11);
 //      the label (the only one) or its winner-takes-all key.
 // The same arithmetic as the label-lane path, in another summation order.
+// Instantiated per channel count in generated units (every cost type and
+// solve mode of one n per unit).
+#pragma once
+
+#include <type_traits>
+
 #include "hgf_launch.hpp"
 
 namespace hgf {
-namespace {
+namespace sk {
 
 constexpr int kSingleBand = 32;  // rows per thread of the vertical passes
 
@@ -81,14 +87,18 @@ __device__ __forceinline__ double hsum(const float* __restrict__ img, size_t row
 }
 
 // Horizontal sums and the per-pixel solve; coefficient images [NG+1][P].
-template <int NG, int RIDGE>
+// Both covariance records are applied in float64 here (the float32 record's
+// elements widened), the ridge inverse too.
+template <int NG, int MODE>
 __global__ __launch_bounds__(256) void single_solve_kernel(const float* __restrict__ vbox,
                                                            const void* __restrict__ minv_void,
                                                            float* __restrict__ coef, int H,
                                                            int W, int R) {
   constexpr int NCH = NG + 1;
+  constexpr bool RIDGE = MODE == kSolveRidge;
   constexpr int D = RIDGE ? NCH : NG;
-  constexpr int RW = minv_stride(RIDGE, NG);
+  constexpr int RW = minv_stride(MODE, NG);
+  using MT = typename std::conditional<MODE == kSolveCov32, float, double>::type;
   const size_t P = static_cast<size_t>(H) * W;
   const size_t p = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
   if (p >= P) return;
@@ -98,9 +108,9 @@ __global__ __launch_bounds__(256) void single_solve_kernel(const float* __restri
   double T[NCH];
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) T[ch] = hsum(vbox + ch * P, row, x, W, R);
-  if (!RIDGE) {
-    // record: mu_1..mu_n, then the packed inverse (float32)
-    const float* __restrict__ rec = static_cast<const float*>(minv_void) + p * RW;
+  if constexpr (!RIDGE) {
+    // record: mu_1..mu_n, then the packed inverse
+    const MT* __restrict__ rec = static_cast<const MT*>(minv_void) + p * RW;
     const double invN = 1.0 / static_cast<double>(window_count(x, y, W, H, R));
     const double U = T[0];
     double c[NG], av[NG];
@@ -172,8 +182,11 @@ __global__ __launch_bounds__(256) void single_out_kernel(const float* __restrict
     atomicMin(&keys[p], wta_key(zf, label));
 }
 
+}  // namespace sk
+
 template <int NG, typename TIN>
 hipError_t single_launch_t(const SingleLaunch& a, hipStream_t s) {
+  using namespace sk;
   constexpr int NCH = NG + 1;
   const size_t P = static_cast<size_t>(a.H) * a.W;
   float* v = a.ws;             // vertical sums [NCH][P]
@@ -183,12 +196,15 @@ hipError_t single_launch_t(const SingleLaunch& a, hipStream_t s) {
   const unsigned pgrid = static_cast<unsigned>((P + 255) / 256);
   hipLaunchKernelGGL((single_vbox_kernel<NCH, 1, TIN>), vgrid, dim3(256), 0, s, a.g32,
                      static_cast<const TIN*>(a.cost), a.cost_ld, nullptr, v, a.H, a.W, a.R);
-  if (a.reg == 0)
-    hipLaunchKernelGGL((single_solve_kernel<NG, 0>), dim3(pgrid), dim3(256), 0, s, v, a.minv, c,
-                       a.H, a.W, a.R);
+  if (a.mode == kSolveCov32)
+    hipLaunchKernelGGL((single_solve_kernel<NG, kSolveCov32>), dim3(pgrid), dim3(256), 0, s, v,
+                       a.minv, c, a.H, a.W, a.R);
+  else if (a.mode == kSolveCov64)
+    hipLaunchKernelGGL((single_solve_kernel<NG, kSolveCov64>), dim3(pgrid), dim3(256), 0, s, v,
+                       a.minv, c, a.H, a.W, a.R);
   else
-    hipLaunchKernelGGL((single_solve_kernel<NG, 1>), dim3(pgrid), dim3(256), 0, s, v, a.minv, c,
-                       a.H, a.W, a.R);
+    hipLaunchKernelGGL((single_solve_kernel<NG, kSolveRidge>), dim3(pgrid), dim3(256), 0, s, v,
+                       a.minv, c, a.H, a.W, a.R);
   hipLaunchKernelGGL((single_vbox_kernel<NCH, 0, float>), vgrid, dim3(256), 0, s, nullptr,
                      static_cast<const float*>(nullptr), 0, c, v, a.H, a.W, a.R);
   hipLaunchKernelGGL((single_out_kernel<NG>), dim3(pgrid), dim3(256), 0, s, v, a.g32, a.out,
@@ -196,26 +212,13 @@ hipError_t single_launch_t(const SingleLaunch& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Every cost type of one channel count.
 template <int NG>
 hipError_t single_launch_n(const SingleLaunch& a, hipStream_t s) {
-  if (a.cost_bf16) return single_launch_t<NG, uint16_t>(a, s);
-  return single_launch_t<NG, float>(a, s);
-}
-
-}  // namespace
-
-hipError_t launch_single(const SingleLaunch& a, hipStream_t s) {
-  switch (a.n) {
-    case 1: return single_launch_n<1>(a, s);
-    case 2: return single_launch_n<2>(a, s);
-    case 3: return single_launch_n<3>(a, s);
-    case 4: return single_launch_n<4>(a, s);
-    case 5: return single_launch_n<5>(a, s);
-    case 6: return single_launch_n<6>(a, s);
-    case 7: return single_launch_n<7>(a, s);
-    case 8: return single_launch_n<8>(a, s);
-    case 9: return single_launch_n<9>(a, s);
-    case 19: return single_launch_n<19>(a, s);
+  switch (a.cost_type) {
+    case kCostF32: return single_launch_t<NG, float>(a, s);
+    case kCostBF16: return single_launch_t<NG, bf16_t>(a, s);
+    case kCostF16: return single_launch_t<NG, f16_t>(a, s);
     default: return hipErrorNotSupported;
   }
 }

@@ -50,27 +50,25 @@ hgf_status time_path(hgf_context* ctx, const Plan& pl, const float* guide, const
   return HGF_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-hgf_status hgf_autotune(hgf_context* ctx, const hgf_params* params, const float* guide,
-                        const void* cost, float* out, void* workspace, size_t workspace_bytes,
-                        void* hip_stream) {
+hgf_status autotune(hgf_context* ctx, const hgf_params* params, const float* guide,
+                    const void* cost, float* out, void* workspace, size_t workspace_bytes,
+                    void* hip_stream) {
   if (ctx == nullptr) return fail(HGF_E_INVALID, "context is NULL");
   MonoTable t;
   hgf_status st = validate(params, &t);
   if (st != HGF_OK) return st;
   if (guide == nullptr || cost == nullptr) return fail(HGF_E_INVALID, "guide or cost is NULL");
-  const Plan pl = make_plan(params, t, (params->num_labels + 63) / 64);
+  const Plan pl = make_plan(params, t, (params->num_labels + 63) / 64, ctx->group_bytes);
   void* ws = workspace;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (ws == nullptr) {
     st = ctx_scratch(ctx, pl.total, &ws);
+    if (st != HGF_OK) return st;
+    st = mark_used(&ctx->scratch_used, s);
     if (st != HGF_OK) return st;
   } else if (workspace_bytes < pl.total) {
     return fail(HGF_E_INVALID, "workspace smaller than hgf_workspace_size()");
   }
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int cost_ld = params->cost_ld ? params->cost_ld : params->num_labels;
   const int out_ld = params->out_ld ? params->out_ld : params->num_labels;
   double ms[HGF_NUM_STAGES];
@@ -101,11 +99,28 @@ hgf_status hgf_autotune(hgf_context* ctx, const hgf_params* params, const float*
   for (int k = 0; k < 3; ++k) ctx->tune[keys[k]] = arg[k];
   // leave `out` holding what hgf_filter now computes with the chosen table
   if (out != nullptr) st = time_path(ctx, pl, guide, cost, cost_ld, out, out_ld, ws, 1, s, ms);
+  if (workspace == nullptr) {
+    const hgf_status m = mark_used(&ctx->scratch_used, s);
+    if (st == HGF_OK) st = m;
+  }
   return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+hgf_status hgf_autotune(hgf_context* ctx, const hgf_params* params, const float* guide,
+                        const void* cost, float* out, void* workspace, size_t workspace_bytes,
+                        void* hip_stream) {
+  return guarded(ctx, [&] {
+    return autotune(ctx, params, guide, cost, out, workspace, workspace_bytes, hip_stream);
+  });
 }
 
 hgf_status hgf_tune_entries(const hgf_context* ctx, int32_t* rows, int32_t max_rows,
                             int32_t* count) {
+  return guarded(const_cast<hgf_context*>(ctx), [&]() -> hgf_status {
   if (ctx == nullptr || count == nullptr) return fail(HGF_E_INVALID, "context or count is NULL");
   int32_t i = 0;
   for (const auto& kv : ctx->tune) {
@@ -123,33 +138,39 @@ hgf_status hgf_tune_entries(const hgf_context* ctx, int32_t* rows, int32_t max_r
   }
   *count = i;
   return HGF_OK;
+  });
 }
 
 hgf_status hgf_tune_set(hgf_context* ctx, const int32_t* row) {
-  if (ctx == nullptr || row == nullptr) return fail(HGF_E_INVALID, "context or row is NULL");
-  if (row[0] < 0 || row[0] > 2 || row[6] < 1)
-    return fail(HGF_E_INVALID, "tuning row: kernel in {0,1,2}, target >= 1");
-  ctx->tune[TuneKey(row[0], row[1], row[2], row[3], row[4], row[5])] = row[6];
-  return HGF_OK;
+  return guarded(ctx, [&]() -> hgf_status {
+    if (ctx == nullptr || row == nullptr) return fail(HGF_E_INVALID, "context or row is NULL");
+    if (row[0] < 0 || row[0] > 2 || row[6] < 1)
+      return fail(HGF_E_INVALID, "tuning row: kernel in {0,1,2}, target >= 1");
+    ctx->tune[TuneKey(row[0], row[1], row[2], row[3], row[4], row[5])] = row[6];
+    return HGF_OK;
+  });
 }
 
 hgf_status hgf_tune_save(const hgf_context* ctx, const char* path) {
+  return guarded(const_cast<hgf_context*>(ctx), [&]() -> hgf_status {
   if (ctx == nullptr || path == nullptr) return fail(HGF_E_INVALID, "context or path is NULL");
   FILE* f = std::fopen(path, "w");
-  if (f == nullptr) return fail(HGF_E_INVALID, std::string("cannot write ") + path);
-  std::fprintf(f, "# kernel n radius reg bf16 size_class target_blocks\n");
+  if (f == nullptr) return fail(HGF_E_INVALID, "cannot write %s", path);
+  std::fprintf(f, "# kernel n radius reg cost_dtype size_class target_blocks\n");
   for (const auto& kv : ctx->tune)
     std::fprintf(f, "%d %d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
                  std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first),
                  std::get<5>(kv.first), kv.second);
   std::fclose(f);
   return HGF_OK;
+  });
 }
 
 hgf_status hgf_tune_load(hgf_context* ctx, const char* path) {
+  return guarded(ctx, [&]() -> hgf_status {
   if (ctx == nullptr || path == nullptr) return fail(HGF_E_INVALID, "context or path is NULL");
   FILE* f = std::fopen(path, "r");
-  if (f == nullptr) return fail(HGF_E_INVALID, std::string("cannot read ") + path);
+  if (f == nullptr) return fail(HGF_E_INVALID, "cannot read %s", path);
   char line[256];
   hgf_status st = HGF_OK;
   while (std::fgets(line, sizeof(line), f) != nullptr) {
@@ -157,7 +178,7 @@ hgf_status hgf_tune_load(hgf_context* ctx, const char* path) {
     int32_t r[7];
     if (std::sscanf(line, "%d %d %d %d %d %d %d", &r[0], &r[1], &r[2], &r[3], &r[4], &r[5],
                     &r[6]) != 7) {
-      st = fail(HGF_E_INVALID, std::string("malformed tuning line: ") + line);
+      st = fail(HGF_E_INVALID, "malformed tuning line: %s", line);
       break;
     }
     st = hgf_tune_set(ctx, r);
@@ -165,6 +186,7 @@ hgf_status hgf_tune_load(hgf_context* ctx, const char* path) {
   }
   std::fclose(f);
   return st;
+  });
 }
 
 }  // extern "C"

@@ -5,9 +5,9 @@ device memory (``torch.empty(..., device="cuda")``) and the current stream.
 There is no fallback: if the library is not built, or no GPU is present,
 the calls raise.
 
-Names follow include/hgf.h.  Layouts: guide float32 [m][H][W]; cost float32 or
-bfloat16 [H][W][L] (labels contiguous); filtered costs float32 [H][W][L];
-labels int32 [H][W].
+Names follow include/hgf.h.  Layouts: guide float32 [m][H][W]; cost float32,
+bfloat16 or float16 [H][W][L] (labels contiguous); filtered costs float32
+[H][W][L]; labels int32 [H][W].
 """
 from __future__ import annotations
 
@@ -23,7 +23,9 @@ LIB_PATH = os.path.join(_PKG, "libhgf.so")
 HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "hgf.h")
 
 HGF_OK, HGF_E_INVALID, HGF_E_NOMEM, HGF_E_DEVICE, HGF_E_UNSUPPORTED, HGF_E_BUSY = 0, -1, -2, -3, -4, -5
-HGF_F32, HGF_BF16 = 0, 1
+HGF_F32, HGF_BF16, HGF_F16, HGF_F64 = 0, 1, 2, 3
+COST_DTYPES = {"f32": HGF_F32, "bf16": HGF_BF16, "f16": HGF_F16}
+STATS_DTYPES = {"f32": HGF_F32, "f64": HGF_F64}
 BASIS = {"monomial": 0, "power": 1}
 REG = {"covariance": 0, "ridge": 1}
 STAGES = ["guide_mean", "guide_synth", "guide_moments", "guide_invert", "coef", "out_wta", "wta_keys"]
@@ -54,15 +56,24 @@ class Params(ctypes.Structure):
         ("radius", ctypes.c_int32), ("num_labels", ctypes.c_int32),
         ("eps", ctypes.c_double),
         ("cost_dtype", ctypes.c_int32), ("cost_ld", ctypes.c_int32),
-        ("out_ld", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("out_ld", ctypes.c_int32), ("stats_dtype", ctypes.c_int32),
     ]
 
 
 def make_params(height: int, width: int, labels: int, *, radius: int, eps: float, degree: int,
                 guide_channels: int = 3, basis: str = "monomial", reg: str = "covariance",
-                cost_dtype: str = "f32", cost_ld: int = 0, out_ld: int = 0) -> Params:
+                cost_dtype: str = "f32", cost_ld: int = 0, out_ld: int = 0,
+                stats_dtype: str = "f32") -> Params:
     return Params(height, width, guide_channels, degree, BASIS[basis], REG[reg], radius, labels,
-                  float(eps), HGF_BF16 if cost_dtype == "bf16" else HGF_F32, cost_ld, out_ld, 0)
+                  float(eps), COST_DTYPES[cost_dtype], cost_ld, out_ld, STATS_DTYPES[stats_dtype])
+
+
+_TORCH_COST = {torch.float32: "f32", torch.bfloat16: "bf16", torch.float16: "f16"}
+_COST_TYPES = tuple(_TORCH_COST)
+
+
+def cost_dtype_of(t: torch.Tensor) -> str:
+    return _TORCH_COST[t.dtype]
 
 
 _lib = None
@@ -77,6 +88,7 @@ def _declare(lib):
         "hgf_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(_vp)]),
         "hgf_destroy": (None, [_vp]),
         "hgf_workspace_size": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
+        "hgf_set_group_bytes": (ctypes.c_int, [_vp, ctypes.c_size_t]),
         "hgf_filter": (ctypes.c_int, [_vp, P, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
         "hgf_guide_create": (ctypes.c_int, [_vp, P, _vp, _vp, ctypes.POINTER(_vp)]),
         "hgf_guide_filter": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
@@ -105,7 +117,7 @@ def _declare(lib):
         "hgf_set_stage_timing": (ctypes.c_int, [_vp, ctypes.c_int32]),
         "hgf_stage_times": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
         "hgf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
-        "hgf_last_error": (ctypes.c_char_p, []),
+        "hgf_last_error": (ctypes.c_char_p, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -131,9 +143,11 @@ def header_functions() -> list[str]:
     return sorted(set(re.findall(r"\b(hgf_[a-z_0-9]+)\s*\(", text)))
 
 
-def _check(status: int, where: str):
+def _check(status: int, where: str, ctx=None):
+    """Raise on a failed call; ``ctx`` is the context handle the call took (its
+    detail string), or None for calls without one."""
     if status != HGF_OK:
-        detail = lib().hgf_last_error().decode(errors="replace")
+        detail = lib().hgf_last_error(ctx).decode(errors="replace")
         raise HGFError(status, where, detail)
 
 
@@ -189,34 +203,38 @@ class Context:
         except Exception:
             pass
 
+    def set_group_bytes(self, nbytes: int):
+        """Upper bound of one launch group's coefficient workspace (0 = default 12 GiB)."""
+        _check(lib().hgf_set_group_bytes(self.handle, nbytes), "hgf_set_group_bytes", self.handle)
+
     # -- per-stage event timing ---------------------------------------------
     def set_stage_timing(self, enable: bool):
-        _check(lib().hgf_set_stage_timing(self.handle, 1 if enable else 0), "hgf_set_stage_timing")
+        _check(lib().hgf_set_stage_timing(self.handle, 1 if enable else 0), "hgf_set_stage_timing", self.handle)
 
     def stage_times(self):
         """{stage name: (milliseconds summed, launches)} since the last call; waits for the events."""
         n = len(STAGES)
         ms = (ctypes.c_double * n)()
         cnt = (ctypes.c_int32 * n)()
-        _check(lib().hgf_stage_times(self.handle, ms, cnt, n), "hgf_stage_times")
+        _check(lib().hgf_stage_times(self.handle, ms, cnt, n), "hgf_stage_times", self.handle)
         return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
 
     # -- plain path ---------------------------------------------------------
     def filter(self, guide: torch.Tensor, cost: torch.Tensor, *, radius: int, eps: float,
                degree: int, basis: str = "monomial", reg: str = "covariance",
-               want_out: bool = True, want_labels: bool = True, out: Optional[torch.Tensor] = None,
+               stats_dtype: str = "f32", want_out: bool = True, want_labels: bool = True, out: Optional[torch.Tensor] = None,
                labels: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
                stream=None):
         """Filter every label slice of ``cost`` under ``guide``; returns (Z, labels)."""
         _need_cuda(guide, "guide", (torch.float32,))
-        _need_cuda(cost, "cost", (torch.float32, torch.bfloat16))
+        _need_cuda(cost, "cost", _COST_TYPES)
         m, H, W = guide.shape
         if cost.dim() != 3 or cost.shape[0] != H or cost.shape[1] != W:
             raise ValueError("cost must be [H][W][L] with the guide's H and W")
         L = cost.shape[2]
         p = make_params(H, W, L, radius=radius, eps=eps, degree=degree, guide_channels=m,
                         basis=basis, reg=reg,
-                        cost_dtype="bf16" if cost.dtype == torch.bfloat16 else "f32")
+                        cost_dtype=cost_dtype_of(cost), stats_dtype=stats_dtype)
         if want_out and out is None:
             out = torch.empty((H, W, L), dtype=torch.float32, device=guide.device)
         if want_labels and labels is None:
@@ -226,43 +244,43 @@ class Context:
         _check(lib().hgf_filter(self.handle, ctypes.byref(p), _ptr(guide), _ptr(cost),
                                 _ptr(out if want_out else None),
                                 _ptr(labels if want_labels else None), _ptr(workspace),
-                                workspace.numel(), _stream(stream)), "hgf_filter")
+                                workspace.numel(), _stream(stream)), "hgf_filter", self.handle)
         return (out if want_out else None), (labels if want_labels else None)
 
     # -- tuning table ------------------------------------------------------
     def autotune(self, guide: torch.Tensor, cost: torch.Tensor, *, radius: int, eps: float,
                  degree: int, basis: str = "monomial", reg: str = "covariance",
+                 stats_dtype: str = "f32",
                  out: Optional[torch.Tensor] = None, stream=None):
         """Time the strip-decomposition candidates on these inputs and keep the fastest."""
         _need_cuda(guide, "guide", (torch.float32,))
-        _need_cuda(cost, "cost", (torch.float32, torch.bfloat16))
+        _need_cuda(cost, "cost", _COST_TYPES)
         m, H, W = guide.shape
         L = cost.shape[2]
         p = make_params(H, W, L, radius=radius, eps=eps, degree=degree, guide_channels=m,
                         basis=basis, reg=reg,
-                        cost_dtype="bf16" if cost.dtype == torch.bfloat16 else "f32")
+                        cost_dtype=cost_dtype_of(cost), stats_dtype=stats_dtype)
         ws = torch.empty(workspace_size(p), dtype=torch.uint8, device=guide.device)
         _check(lib().hgf_autotune(self.handle, ctypes.byref(p), _ptr(guide), _ptr(cost), _ptr(out),
-                                  _ptr(ws), ws.numel(), _stream(stream)), "hgf_autotune")
+                                  _ptr(ws), ws.numel(), _stream(stream)), "hgf_autotune", self.handle)
 
     def tune_entries(self) -> list[tuple[int, ...]]:
         """Rows (kernel, n, radius, reg, bf16, size_class, target_blocks) of the tuning table."""
         cnt = ctypes.c_int32(0)
-        _check(lib().hgf_tune_entries(self.handle, None, 0, ctypes.byref(cnt)), "hgf_tune_entries")
+        _check(lib().hgf_tune_entries(self.handle, None, 0, ctypes.byref(cnt)), "hgf_tune_entries", self.handle)
         rows = (ctypes.c_int32 * (7 * max(1, cnt.value)))()
-        _check(lib().hgf_tune_entries(self.handle, rows, cnt.value, ctypes.byref(cnt)),
-               "hgf_tune_entries")
+        _check(lib().hgf_tune_entries(self.handle, rows, cnt.value, ctypes.byref(cnt)), "hgf_tune_entries", self.handle)
         return [tuple(int(rows[7 * i + k]) for k in range(7)) for i in range(cnt.value)]
 
     def tune_set(self, row: Sequence[int]):
         arr = (ctypes.c_int32 * 7)(*row)
-        _check(lib().hgf_tune_set(self.handle, arr), "hgf_tune_set")
+        _check(lib().hgf_tune_set(self.handle, arr), "hgf_tune_set", self.handle)
 
     def tune_save(self, path: str):
-        _check(lib().hgf_tune_save(self.handle, os.fsencode(path)), "hgf_tune_save")
+        _check(lib().hgf_tune_save(self.handle, os.fsencode(path)), "hgf_tune_save", self.handle)
 
     def tune_load(self, path: str):
-        _check(lib().hgf_tune_load(self.handle, os.fsencode(path)), "hgf_tune_load")
+        _check(lib().hgf_tune_load(self.handle, os.fsencode(path)), "hgf_tune_load", self.handle)
 
     # -- batched path -------------------------------------------------------
     def filter_batch(self, items: Sequence[dict], stream=None, outputs=None):
@@ -281,13 +299,14 @@ class Context:
         for i, it in enumerate(items):
             g, c = it["guide"], it["cost"]
             _need_cuda(g, "guide", (torch.float32,))
-            _need_cuda(c, "cost", (torch.float32, torch.bfloat16))
+            _need_cuda(c, "cost", _COST_TYPES)
             m, H, W = g.shape
             L = c.shape[2]
             arr[i] = make_params(H, W, L, radius=it["radius"], eps=it["eps"], degree=it["degree"],
                                  guide_channels=m, basis=it.get("basis", "monomial"),
                                  reg=it.get("reg", "covariance"),
-                                 cost_dtype="bf16" if c.dtype == torch.bfloat16 else "f32")
+                                 cost_dtype=cost_dtype_of(c),
+                                 stats_dtype=it.get("stats_dtype", "f32"))
             if outputs is not None:
                 z, lb = outputs[i]
                 _need_cuda(z, "out", (torch.float32,))
@@ -300,7 +319,7 @@ class Context:
             guides[i], costs[i], outs[i], labs[i] = g.data_ptr(), c.data_ptr(), z.data_ptr(), lb.data_ptr()
             results.append((z, lb))
         _check(lib().hgf_filter_batch(self.handle, n, arr, guides, costs, outs, labs,
-                                      _stream(stream)), "hgf_filter_batch")
+                                      _stream(stream)), "hgf_filter_batch", self.handle)
         return results
 
 
@@ -310,47 +329,46 @@ class Server:
     def __init__(self, ctx: Context, *, slots: int = 4, arena_bytes: int = 8 << 30,
                  max_queue: int = 1024):
         h = ctypes.c_void_p()
-        _check(lib().hgf_server_create(ctx.handle, slots, arena_bytes, max_queue, ctypes.byref(h)),
-               "hgf_server_create")
+        _check(lib().hgf_server_create(ctx.handle, slots, arena_bytes, max_queue, ctypes.byref(h)), "hgf_server_create", ctx.handle)
         self.handle = h
         self.ctx = ctx
 
     def submit(self, guide: torch.Tensor, cost: torch.Tensor, out: Optional[torch.Tensor],
                labels: Optional[torch.Tensor], *, radius: int, eps: float, degree: int,
-               basis: str = "monomial", reg: str = "covariance", stream=None) -> int:
+               basis: str = "monomial", reg: str = "covariance", stats_dtype: str = "f32",
+               stream=None) -> int:
         """Queue one request; the caller keeps every tensor alive until it completes."""
         _need_cuda(guide, "guide", (torch.float32,))
-        _need_cuda(cost, "cost", (torch.float32, torch.bfloat16))
+        _need_cuda(cost, "cost", _COST_TYPES)
         m, H, W = guide.shape
         L = cost.shape[2]
         p = make_params(H, W, L, radius=radius, eps=eps, degree=degree, guide_channels=m,
                         basis=basis, reg=reg,
-                        cost_dtype="bf16" if cost.dtype == torch.bfloat16 else "f32")
+                        cost_dtype=cost_dtype_of(cost), stats_dtype=stats_dtype)
         rid = ctypes.c_int64(-1)
         _check(lib().hgf_server_submit(self.handle, ctypes.byref(p), _ptr(guide), _ptr(cost),
                                        _ptr(out), _ptr(labels), _stream(stream),
-                                       ctypes.byref(rid)), "hgf_server_submit")
+                                       ctypes.byref(rid)), "hgf_server_submit", self.ctx.handle)
         return int(rid.value)
 
     def poll(self, max_done: int = 256) -> list[Completion]:
         buf = (Completion * max_done)()
         cnt = ctypes.c_int32(0)
-        _check(lib().hgf_server_poll(self.handle, buf, max_done, ctypes.byref(cnt)),
-               "hgf_server_poll")
+        _check(lib().hgf_server_poll(self.handle, buf, max_done, ctypes.byref(cnt)), "hgf_server_poll", self.ctx.handle)
         return [buf[i] for i in range(cnt.value)]
 
     def drain(self):
-        _check(lib().hgf_server_drain(self.handle), "hgf_server_drain")
+        _check(lib().hgf_server_drain(self.handle), "hgf_server_drain", self.ctx.handle)
 
     def now_ms(self) -> float:
         """Device clock in ms since the server was created."""
         t = ctypes.c_double(0.0)
-        _check(lib().hgf_server_now(self.handle, ctypes.byref(t)), "hgf_server_now")
+        _check(lib().hgf_server_now(self.handle, ctypes.byref(t)), "hgf_server_now", self.ctx.handle)
         return float(t.value)
 
     def stats(self) -> dict:
         info = ServerInfo()
-        _check(lib().hgf_server_stats(self.handle, ctypes.byref(info)), "hgf_server_stats")
+        _check(lib().hgf_server_stats(self.handle, ctypes.byref(info)), "hgf_server_stats", self.ctx.handle)
         return {k: int(getattr(info, k)) for k, _ in ServerInfo._fields_}
 
     def close(self):
@@ -370,7 +388,7 @@ class Guide:
 
     def __init__(self, ctx: Context, guide: torch.Tensor, *, labels: int, radius: int, eps: float,
                  degree: int, basis: str = "monomial", reg: str = "covariance",
-                 cost_dtype: str = "f32", stream=None):
+                 cost_dtype: str = "f32", stats_dtype: str = "f32", stream=None):
         _need_cuda(guide, "guide", (torch.float32,))
         m, H, W = guide.shape
         self.ctx = ctx
@@ -378,10 +396,11 @@ class Guide:
         self.labels = labels
         self.cost_dtype = cost_dtype
         self.params = make_params(H, W, labels, radius=radius, eps=eps, degree=degree,
-                                  guide_channels=m, basis=basis, reg=reg, cost_dtype=cost_dtype)
+                                  guide_channels=m, basis=basis, reg=reg, cost_dtype=cost_dtype,
+                                  stats_dtype=stats_dtype)
         h = ctypes.c_void_p()
         _check(lib().hgf_guide_create(ctx.handle, ctypes.byref(self.params), _ptr(guide),
-                                      _stream(stream), ctypes.byref(h)), "hgf_guide_create")
+                                      _stream(stream), ctypes.byref(h)), "hgf_guide_create", ctx.handle)
         self.handle = h
         self.n = num_channels(m, degree, basis)
         self.dim = self.n + 1 if reg == "ridge" else self.n
@@ -393,24 +412,26 @@ class Guide:
     def filter(self, cost_chunk: torch.Tensor, label_begin: int, *, out: Optional[torch.Tensor] = None,
                best: Optional[torch.Tensor] = None, labels: Optional[torch.Tensor] = None,
                stream=None):
-        _need_cuda(cost_chunk, "cost_chunk", (torch.float32, torch.bfloat16))
+        _need_cuda(cost_chunk, "cost_chunk", _COST_TYPES)
         count = cost_chunk.shape[2]
         _check(lib().hgf_guide_filter(self.ctx.handle, self.handle, _ptr(cost_chunk), label_begin,
                                       count, cost_chunk.shape[2], _ptr(out), _ptr(best),
-                                      _ptr(labels), _stream(stream)), "hgf_guide_filter")
+                                      _ptr(labels), _stream(stream)), "hgf_guide_filter", self.ctx.handle)
         return out, best, labels
 
     def export(self, stream=None):
         """(mu [H][W][n] float64, packed inverse [H][W][D(D+1)/2] (float32 in the
-        covariance form, float64 in the ridge form), shift [n] float64) as device tensors."""
+        covariance form with float32 statistics, float64 otherwise), shift [n]
+        float64) as device tensors."""
         H, W = self.shape
         dev = torch.device("cuda", self.ctx.device)
         mu = torch.empty((H, W, self.n), dtype=torch.float64, device=dev)
-        mdt = torch.float64 if self.params.reg == REG["ridge"] else torch.float32
+        mdt = (torch.float32 if self.params.reg == REG["covariance"]
+               and self.params.stats_dtype == HGF_F32 else torch.float64)
         minv = torch.empty((H, W, self.dim * (self.dim + 1) // 2), dtype=mdt, device=dev)
         shift = torch.empty((self.n,), dtype=torch.float64, device=dev)
         _check(lib().hgf_guide_export(self.handle, _ptr(mu), _ptr(minv), _ptr(shift),
-                                      _stream(stream)), "hgf_guide_export")
+                                      _stream(stream)), "hgf_guide_export", self.ctx.handle)
         return mu, minv, shift
 
     def close(self):

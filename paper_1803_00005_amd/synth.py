@@ -38,6 +38,7 @@ __all__ = [
     "make_workload_device",
     "make_batch_specs",
     "make_request_specs",
+    "round_cost",
     "voronoi_regions",
 ]
 
@@ -60,7 +61,7 @@ class Workload:
     basis: str = "monomial"   # "monomial" | "power"
     sigma_guide: float = 0.02
     sigma_cost: float = 0.01
-    cost_dtype: str = "f32"   # "f32" | "bf16"
+    cost_dtype: str = "f32"   # "f32" | "bf16" | "f16"
 
     @property
     def pixels(self) -> int:
@@ -96,6 +97,10 @@ WORKLOADS = {
         name="voronoi1242x375_n19_L128_bf16", height=375, width=1242,
         regions=80, labels=128, radius=9, eps=1e-3, degree=3,
         disparity="planar", seed=3, cost_dtype="bf16"),
+    "voronoi1242x375_n19_L128_f16": Workload(
+        name="voronoi1242x375_n19_L128_f16", height=375, width=1242,
+        regions=80, labels=128, radius=9, eps=1e-3, degree=3,
+        disparity="planar", seed=3, cost_dtype="f16"),
 }
 
 
@@ -152,14 +157,25 @@ def _round_bf16(x: np.ndarray) -> np.ndarray:
     return b.astype(np.uint32).view(np.float32)
 
 
+def round_cost(cost: np.ndarray, cost_dtype: str) -> np.ndarray:
+    """Float32 costs rounded to the values of ``cost_dtype`` (round to nearest
+    even), kept as float32."""
+    if cost_dtype == "bf16":
+        return _round_bf16(cost)
+    if cost_dtype == "f16":
+        return np.ascontiguousarray(cost, dtype=np.float32).astype(np.float16).astype(np.float32)
+    return cost
+
+
 def make_workload(w: Workload, *, with_disparity: bool = False,
                   labels_override: Optional[int] = None):
     """Draw the guide image and cost volume of workload ``w``.
 
-    Returns ``(guide, cost)`` or ``(guide, cost, disp)``.  For ``bf16`` cost
-    workloads the returned float32 cost is already rounded to bfloat16
-    values (round to nearest even), so the oracle and the GPU see the same
-    numbers.
+    Returns ``(guide, cost)`` or ``(guide, cost, disp)``.  For ``bf16`` and
+    ``f16`` cost workloads the returned float32 cost is already rounded to
+    the values of that type (round to nearest even), so the oracle and the
+    GPU see the same numbers; the same workload with ``cost_dtype="f32"``
+    gives the unrounded costs.
     """
     if labels_override is not None:
         w = dataclasses.replace(w, labels=labels_override)
@@ -180,8 +196,7 @@ def make_workload(w: Workload, *, with_disparity: bool = False,
         base = np.minimum(np.abs(lab[None, None, :] - disp[y0:y1, :, None]) / 16.0, 0.5)
         noise = rng.normal(0.0, w.sigma_cost, size=base.shape)
         cost[y0:y1] = (base + noise).astype(np.float32)
-    if w.cost_dtype == "bf16":
-        cost = _round_bf16(cost)
+    cost = round_cost(cost, w.cost_dtype)
     if with_disparity:
         return guide, cost, disp
     return guide, cost
@@ -195,8 +210,8 @@ def make_workload_device(w: Workload, device):
     the order and distributions of ``make_workload`` but come from a
     ``torch.Generator`` seeded with ``w.seed``, so the values differ from the
     host generator's.  Returns ``(guide, cost)`` as device tensors: guide
-    float32 [m][H][W], cost [H][W][L] float32, or bfloat16 (round to nearest
-    even) for ``bf16`` workloads.
+    float32 [m][H][W], cost [H][W][L] float32, or bfloat16 / float16 (round
+    to nearest even) for ``bf16`` / ``f16`` workloads.
     """
     import torch
 
@@ -237,7 +252,7 @@ def make_workload_device(w: Workload, device):
     guide = colours[region].permute(2, 0, 1) + w.sigma_guide * torch.randn(
         m, H, W_, generator=gen, **f64)
     guide = guide.float().contiguous()
-    cdt = torch.bfloat16 if w.cost_dtype == "bf16" else torch.float32
+    cdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[w.cost_dtype]
     cost = torch.empty(H, W_, L, dtype=cdt, device=device)
     lab = torch.arange(L, dtype=torch.float32, device=device)
     rows = max(1, (1 << 26) // max(1, W_ * L))

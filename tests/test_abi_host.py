@@ -30,11 +30,16 @@ def test_num_channels():
 
 
 def test_supported_set():
-    for n in (1, 2, 3, 4, 5, 6, 7, 8, 9, 19):
-        for r in (1, 2, 4, 7, 9):
+    # every channel count 1..19 (e.g. the power basis of RGB at d = 4, n = 12)
+    # and every radius 0..9, in both forms
+    for n in range(1, 20):
+        for r in range(0, 10):
             assert hgf.is_supported(n, r)
-    assert not hgf.is_supported(10, 4)
-    assert not hgf.is_supported(3, 3)
+            assert hgf.is_supported(n, r, "ridge")
+    assert not hgf.is_supported(20, 4)
+    assert not hgf.is_supported(0, 4)
+    assert not hgf.is_supported(3, 10)
+    assert hgf.workspace_size(_p(degree=4, basis="power")) > 0   # n = 12
 
 
 def _p(**kw):
@@ -60,15 +65,17 @@ def test_workspace_size_valid():
     (dict(radius=-1), hgf.HGF_E_INVALID),
     (dict(degree=0), hgf.HGF_E_INVALID),
     (dict(guide_channels=4), hgf.HGF_E_INVALID),
-    (dict(radius=3), hgf.HGF_E_UNSUPPORTED),
+    (dict(radius=10), hgf.HGF_E_UNSUPPORTED),
     (dict(degree=4), hgf.HGF_E_UNSUPPORTED),       # n = 34
     (dict(reg="ridge", cost_dtype="bf16"), hgf.HGF_E_UNSUPPORTED),
+    (dict(reg="ridge", cost_dtype="f16"), hgf.HGF_E_UNSUPPORTED),
 ])
 def test_workspace_size_rejects(bad, status):
     with pytest.raises(hgf.HGFError) as ei:
         hgf.workspace_size(_p(**bad))
     assert ei.value.status == status
-    assert hgf.lib().hgf_last_error()
+    # a call without a context leaves its detail in the thread's string
+    assert hgf.lib().hgf_last_error(None)
 
 
 def test_null_pointer_arguments():
@@ -83,11 +90,21 @@ def test_null_pointer_arguments():
     assert lib.hgf_status_string(hgf.HGF_E_UNSUPPORTED) == b"HGF_E_UNSUPPORTED"
 
 
-def test_reserved_field_must_be_zero():
+@pytest.mark.parametrize("field,value", [("stats_dtype", 1), ("stats_dtype", 2),
+                                         ("stats_dtype", -1), ("cost_dtype", 3),
+                                         ("cost_dtype", 7)])
+def test_dtype_fields_validated(field, value):
     p = _p()
-    p.reserved = 1
-    with pytest.raises(hgf.HGFError):
+    setattr(p, field, value)
+    with pytest.raises(hgf.HGFError) as ei:
         hgf.workspace_size(p)
+    assert ei.value.status == hgf.HGF_E_INVALID
+
+
+def test_float64_solve_records_need_more_workspace():
+    # the float64 solve keeps float64 window means and inverses per pixel
+    assert hgf.workspace_size(_p(stats_dtype="f64")) > hgf.workspace_size(_p())
+    assert hgf.workspace_size(_p(cost_dtype="f16")) == hgf.workspace_size(_p())
 
 
 def test_ld_smaller_than_labels_rejected():

@@ -55,7 +55,7 @@ MIX = [
 
 def inputs(w):
     guide, cost = synth.make_workload(w)
-    cdt = torch.bfloat16 if w.cost_dtype == "bf16" else torch.float32
+    cdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[w.cost_dtype]
     return guide, cost, to_dev(guide), to_dev(cost, cdt)
 
 
@@ -144,7 +144,7 @@ def test_batch_labels_only_entries(data, singles):
     say("batch with labels-only and out-only entries")
     st = lib.hgf_filter_batch(ctx.handle, n, arr, guides, costs, outs, labs,
                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-    assert st == hgf.HGF_OK, lib.hgf_last_error()
+    assert st == hgf.HGF_OK, lib.hgf_last_error(ctx.handle)
     torch.cuda.synchronize()
     for i in range(n):
         Zs, ls = singles[i]
@@ -157,7 +157,7 @@ def test_batch_labels_only_entries(data, singles):
     labs[0] = None
     st = lib.hgf_filter_batch(ctx.handle, n, arr, guides, costs, outs, labs, None)
     assert st == hgf.HGF_E_INVALID
-    assert b"image 0" in lib.hgf_last_error()
+    assert b"image 0" in lib.hgf_last_error(ctx.handle)
     ctx.close()
 
 

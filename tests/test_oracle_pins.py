@@ -366,6 +366,23 @@ def test_filter_points_match_full():
                                Zr[tuple(np.array(pts).T)], rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("mode,r,tiles", [("covariance", 3, (2, 1)), ("ridge", 1, (3, 2)), ("covariance", 1, (1, 1))])
+def test_banded_oracle_equals_whole_image(mode, r, tiles):
+    """The tile driver (output tiles with a 2r halo, in spawned worker processes)
+    reproduces the whole-image oracle: the locality argument of Eq. 7 /
+    Eq. 11 (an output row needs coefficients within r, which need inputs
+    within r) holds exactly, clipped windows included."""
+    from oracle import banded
+    rng = np.random.default_rng(7 + r)
+    I = rng.uniform(0, 1, size=(3, 23, 17))
+    G = O.guidance(I, 2)
+    V = rng.uniform(0, 1, size=(23, 17, 5))
+    full = O.filter_covariance(G, V, r, 1e-3) if mode == "covariance" else O.filter_ridge(G, V, r, 0.05)
+    Zb = banded.filter_image(G, V, r, 1e-3 if mode == "covariance" else 0.05, mode=mode,
+                             tiles=tiles, workers=2, label_chunk=2)
+    np.testing.assert_allclose(Zb, full, rtol=0, atol=1e-12)
+
+
 def test_wta_lowest_label_on_ties_and_near_tie_mask():
     Z = np.array([[[3.0, 1.0, 1.0, 2.0], [0.5, 0.5, 0.1, 0.1]]])
     np.testing.assert_array_equal(O.wta(Z), [[1, 2]])

@@ -52,3 +52,19 @@ def test_batch_and_request_specs_are_seeded():
     t = np.array([r[0] for r in reqs])
     assert np.all(np.diff(t) >= 0) and t[0] == 0.0
     assert all(r[1].n in (9, 19) for r in reqs)
+
+
+def test_rounded_cost_workloads_round_the_float32_costs():
+    import dataclasses
+    w = synth.WORKLOADS["rgb64_n3_L16"]
+    _, c32 = synth.make_workload(w)
+    # round to nearest: within half a unit in the last place of the type
+    # (8 and 11 significand bits; float16 subnormals below 2^-14 have a fixed
+    # spacing of 2^-24)
+    for dt, rel_tol, abs_tol in (("bf16", 2.0 ** -8, 0.0), ("f16", 2.0 ** -11, 2.0 ** -25)):
+        _, c = synth.make_workload(dataclasses.replace(w, cost_dtype=dt))
+        assert np.all(np.abs(c - c32) <= rel_tol * np.abs(c32) + abs_tol)
+        assert np.array_equal(synth.round_cost(c, dt), c)   # already representable
+    # f16 values are exactly what numpy's float16 conversion gives
+    _, c16 = synth.make_workload(dataclasses.replace(w, cost_dtype="f16"))
+    assert np.array_equal(c16, c32.astype(np.float16).astype(np.float32))
