@@ -441,34 +441,47 @@ def secondary_batch(ctx, count, steps, warmup, check):
 # serving form: open-loop Poisson arrivals through the serving queue
 # ----------------------------------------------------------------------------
 
-def secondary_serve(ctx, requests, pool, rate, slots, arena_gb):
+class _ServePool:
+    """Device inputs and outputs of the served streams: ``size`` distinct
+    requests drawn from the serving mix (sizes, labels, n, cost dtype), each
+    with its own Voronoi inputs; request k of a stream uses entry k mod size."""
+
+    def __init__(self, size, seed=5):
+        import torch
+        dev = torch.device("cuda", 0)
+        self.specs = [w for _, w in synth.make_request_specs(size, seed=seed)]
+        self.inputs = [synth.make_workload_device(w, dev) for w in self.specs]
+        self.outputs = [(torch.empty(w.height, w.width, w.labels, dtype=torch.float32, device=dev),
+                         torch.empty(w.height, w.width, dtype=torch.int32, device=dev))
+                        for w in self.specs]
+
+
+def _serve_stream(ctx, pool, requests, rate, slots, arena_gb, seed):
+    """One open-loop Poisson stream through the serving queue.  Latency is
+    measured from each request's scheduled arrival to its completion on the
+    device clock (queueing, admission and any wait for a free input buffer
+    included)."""
     import torch
 
     from paper_1803_00005_amd import hgf
-    dev = torch.device("cuda", 0)
-    reqs = synth.make_request_specs(requests, seed=5, rate_per_s=rate)
-    pool = min(pool, requests)
-    say(f"serve: drawing {pool} distinct requests on the device")
-    inputs = [synth.make_workload_device(reqs[j][1], dev) for j in range(pool)]
-    outputs = [(torch.empty(w.height, w.width, w.labels, dtype=torch.float32, device=dev),
-                torch.empty(w.height, w.width, dtype=torch.int32, device=dev))
-               for _, w in reqs[:pool]]
+    npool = len(pool.specs)
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
     srv = hgf.Server(ctx, slots=slots, arena_bytes=int(arena_gb * (1 << 30)),
                      max_queue=requests + 1)
-    # warm-up: every pool entry once, alone
-    for j in range(pool):
-        w = reqs[j][1]
-        srv.submit(inputs[j][0], inputs[j][1], outputs[j][0], outputs[j][1], radius=w.radius,
-                   eps=w.eps, degree=w.degree)
+    # warm-up: every pool entry once, alone (code objects, caches)
+    for j in range(npool):
+        w = pool.specs[j]
+        srv.submit(pool.inputs[j][0], pool.inputs[j][1], pool.outputs[j][0], pool.outputs[j][1],
+                   radius=w.radius, eps=w.eps, degree=w.degree)
         srv.drain()
-    srv.poll(4 * pool)
+    srv.poll(4 * npool)
     torch.cuda.synchronize()
-    say("serve: warm-up done")
     dev0 = srv.now_ms()
     t0 = time.perf_counter()
-    arrivals = [a for a, _ in reqs]
-    done = {}
-    id_of = {}
+    done, id_of = {}, {}
+    last_note = t0
 
     def collect():
         for c in srv.poll(1024):
@@ -477,51 +490,78 @@ def secondary_serve(ctx, requests, pool, rate, slots, arena_gb):
     k = 0
     while k < requests:
         now = time.perf_counter() - t0
+        if time.perf_counter() - last_note > 10.0:
+            say(f"serve: {k} of {requests} submitted, {len(done)} done")
+            last_note = time.perf_counter()
         if now < arrivals[k]:
             collect()
             if arrivals[k] - now > 5e-4:
                 time.sleep(2e-4)
             continue
-        j = k % pool
-        if k >= pool:  # request k reuses the buffers of request k - pool
-            while id_of[k - pool] not in done:
+        j = k % npool
+        if k >= npool:  # request k writes the buffers of request k - npool
+            while id_of[k - npool] not in done:
                 collect()
-        w = reqs[j][1]
-        id_of[k] = srv.submit(inputs[j][0], inputs[j][1], outputs[j][0], outputs[j][1],
-                              radius=w.radius, eps=w.eps, degree=w.degree)
+        w = pool.specs[j]
+        id_of[k] = srv.submit(pool.inputs[j][0], pool.inputs[j][1], pool.outputs[j][0],
+                              pool.outputs[j][1], radius=w.radius, eps=w.eps, degree=w.degree)
         k += 1
     srv.drain()
     collect()
     stats = srv.stats()
+    srv.close()
     lat = np.array([done[id_of[k]].end_ms - (dev0 + 1e3 * arrivals[k]) for k in range(requests)])
-    statuses = {int(done[id_of[k]].status) for k in range(requests)}
-    work = np.array([reqs[k % pool][1].pixel_labels for k in range(requests)], dtype=np.float64)
-    t_end = max(done[id_of[k]].end_ms for k in range(requests))
-    span_ms = t_end - dev0
+    statuses = sorted({int(done[id_of[k]].status) for k in range(requests)})
+    work = np.array([pool.specs[k % npool].pixel_labels for k in range(requests)],
+                    dtype=np.float64)
+    span_ms = max(done[id_of[k]].end_ms for k in range(requests)) - dev0
     offered = work.sum() / max(arrivals[-1], 1e-9) / 1e6
-    # alone vs in the mix: re-run the last use of three pool entries through hgf_filter
+    value = work.sum() / span_ms / 1e3
+    return {"rate_per_s": rate, "requests": requests, "value": value, "unit": UNIT,
+            "offered": offered, "sustained": bool(value >= 0.95 * offered),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                           "p99": float(np.percentile(lat, 99)),
+                           "mean": float(lat.mean()), "max": float(lat.max()),
+                           "first_half_p99": float(np.percentile(lat[:requests // 2], 99)),
+                           "second_half_p99": float(np.percentile(lat[requests // 2:], 99))},
+            "span_s": span_ms / 1e3, "arrival_span_s": float(arrivals[-1]),
+            "arena_peak_gb": stats["arena_peak"] / (1 << 30), "statuses": statuses,
+            "mean_pixel_labels_per_request": float(work.mean())}
+
+
+def secondary_serve(ctx, requests, pool_size, rate, slots, arena_gb, low_rate, low_requests):
+    """The serving form: the Poisson stream of the serving workload (its rate
+    and request count), and a second stream below the device's capacity so
+    that a steady-state p50 / p99 is measured too.  Served results are
+    checked bit for bit against hgf_filter alone."""
+    import torch
+    say(f"serve: drawing {pool_size} distinct requests on the device")
+    pool = _ServePool(pool_size)
+    say(f"serve: stream of {requests} requests at {rate} req/s")
+    main = _serve_stream(ctx, pool, requests, rate, slots, arena_gb, seed=50)
+    say(f"serve: p50 {main['latency_ms']['p50']:.1f} ms p99 {main['latency_ms']['p99']:.1f} ms, "
+        f"{main['value']:.0f} of {main['offered']:.0f} {UNIT} offered")
+    low = None
+    if low_requests > 0:
+        say(f"serve: stream of {low_requests} requests at {low_rate} req/s")
+        low = _serve_stream(ctx, pool, low_requests, low_rate, slots, arena_gb, seed=51)
+        say(f"serve: p50 {low['latency_ms']['p50']:.1f} ms p99 {low['latency_ms']['p99']:.1f} ms "
+            f"at {low_rate} req/s")
+    # alone vs in the mix: the last use of three pool entries through hgf_filter
     same = True
-    for j in range(min(3, pool)):
-        w = reqs[j][1]
-        z, lb = ctx.filter(inputs[j][0], inputs[j][1], radius=w.radius, eps=w.eps,
+    for j in range(min(3, pool_size)):
+        w = pool.specs[j]
+        z, lb = ctx.filter(pool.inputs[j][0], pool.inputs[j][1], radius=w.radius, eps=w.eps,
                            degree=w.degree)
         torch.cuda.synchronize()
-        same = same and torch.equal(z, outputs[j][0]) and torch.equal(lb, outputs[j][1])
-    srv.close()
-    rec = {"form": "serve", "workload": f"poisson{int(rate)}rps_{requests}req", "requests": requests,
-           "distinct_inputs": pool, "slots": slots, "arena_gb": arena_gb,
-           "value": work.sum() / span_ms / 1e3, "unit": UNIT,
-           "offered": offered, "sustained": bool(work.sum() / span_ms / 1e3 >= 0.95 * offered),
-           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                          "mean": float(lat.mean()), "max": float(lat.max())},
-           "mean_pixel_labels_per_request": float(work.mean()),
-           "arena_peak_gb": stats["arena_peak"] / (1 << 30), "statuses": sorted(statuses),
-           "served_equals_alone_bitwise": bool(same),
-           "data": "device-drawn (torch generator), same recipe; request k uses the shape and "
-                   f"inputs of request k mod {pool}"}
-    say(f"serve: p50 {rec['latency_ms']['p50']:.1f} ms p99 {rec['latency_ms']['p99']:.1f} ms, "
-        f"{rec['value']:.0f} of {offered:.0f} {UNIT} offered")
-    del inputs, outputs
+        same = same and torch.equal(z, pool.outputs[j][0]) and torch.equal(lb, pool.outputs[j][1])
+    rec = {"form": "serve", "workload": f"poisson{int(rate)}rps_{requests}req",
+           "distinct_inputs": pool_size, "slots": slots, "arena_gb": arena_gb,
+           **main, "below_capacity": low, "served_equals_alone_bitwise": bool(same),
+           "data": "device-drawn (torch generator), same recipe; request k of a stream uses the "
+                   f"shape and inputs of entry k mod {pool_size} of a pool drawn from the "
+                   "serving mix"}
+    del pool
     torch.cuda.empty_cache()
     return rec
 
@@ -657,9 +697,12 @@ def main():
                     help="comma list of n19, batch, serve, inverse, gray, or 'none'")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=3)
-    ap.add_argument("--serve-requests", type=int, default=400)
-    ap.add_argument("--serve-pool", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-pool", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-low-rate", type=float, default=80.0,
+                    help="rate of the second, below-capacity stream (req/s)")
+    ap.add_argument("--serve-low-requests", type=int, default=1500)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-arena-gb", type=float, default=96.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -744,7 +787,8 @@ def main():
         sec.append(secondary_gray(ctx, check=not args.no_check))
     if "serve" in secondary:
         sec.append(secondary_serve(ctx, args.serve_requests, args.serve_pool, args.serve_rate,
-                                   args.serve_slots, args.serve_arena_gb))
+                                   args.serve_slots, args.serve_arena_gb, args.serve_low_rate,
+                                   args.serve_low_requests))
 
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,

@@ -7,6 +7,10 @@
     python -m paper_1803_00005_amd.profile_summary counters FETCH_DIR WRITE_DIR OUT.json \
         --workload NAME --command "..."
 
+    # VALU, LDS, wave-occupancy and L2 counters (one or more --pmc runs)
+    python -m paper_1803_00005_amd.profile_summary units OUT.md DIR [DIR ...] \
+        --workload NAME --command "..."
+
 The counter runs must include a known-size calibration (``bench.py
 --copy-calibration``: a fill that writes 1 GiB and sums that read 1 GiB).
 The calibration factors scale the raw counters to bytes: factor = known
@@ -134,6 +138,89 @@ def counters(fetch_dir: str, write_dir: str, out: str, workload: str, command: s
         json.dump(rec, fh, indent=1)
 
 
+SIMDS = 256 * 4   # MI355X: 256 CUs of 4 SIMDs
+
+
+def _all_counters(dirs):
+    """{short kernel name: {counter: mean value per dispatch}} over the runs' files."""
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in dirs:
+        for f in _find(d, "counter_collection.csv"):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if not OURS.search(r["Kernel_Name"]):
+                        continue
+                    acc[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(
+                        float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+XCDS = 8          # GRBM_GUI_ACTIVE is counted once per XCD
+
+
+def units(out: str, dirs, workload: str, command: str) -> None:
+    """Per-kernel VALU, LDS, occupancy and L2 figures from raw SQ/TCC/GRBM counters.
+
+    cycles       = GRBM_GUI_ACTIVE / 8 (the counter is summed over the 8 XCDs;
+                   cycles / clock reproduces the kernel's duration)
+    VALU busy    = 4 * SQ_INSTS_VALU / (SIMDs * cycles): the share of SIMD cycles
+                   spent issuing vector ALU instructions (a wave64 instruction
+                   occupies a SIMD for 4 cycles without packed FP32)
+    VALU / wave  = SQ_INSTS_VALU / SQ_WAVES
+    LDS / wave   = SQ_INSTS_LDS / SQ_WAVES
+    LDS conflict = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS
+    waves / CU   = 4 * SQ_WAVE_CYCLES / cycles / 256 (mean resident waves per CU;
+                   SQ_WAVE_CYCLES counts wave residency in units of four cycles,
+                   summed over the CUs)
+    L2 hit       = TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum)
+    """
+    data = _all_counters(dirs)
+    lines = ["# Vector ALU, LDS, occupancy and L2 counters", "",
+             f"Workload: `{workload}`.  Commands (from the repository root on the GPU "
+             "machine, one run per counter group):", "", "```", command, "```", "",
+             "Derived: cycles = GRBM_GUI_ACTIVE / 8 (one count per XCD); VALU busy = "
+             "4 SQ_INSTS_VALU / (1024 SIMDs x cycles); waves / CU = 4 SQ_WAVE_CYCLES / "
+             "cycles / 256; L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS).", "",
+             "| kernel | cycles | VALU busy | VALU instr / wave | LDS instr / wave | LDS bank "
+             "conflicts / LDS cycle | mean waves / CU | L2 hit |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|"]
+
+    def g(c, k, default=None):
+        return c.get(k, default)
+
+    raw = {}
+    for k in sorted(data, key=lambda k: -data[k].get("GRBM_GUI_ACTIVE", 0.0)):
+        c = data[k]
+        cyc = busy = vpw = lpw = conf = occ = hit = None
+        if g(c, "GRBM_GUI_ACTIVE"):
+            cyc = c["GRBM_GUI_ACTIVE"] / XCDS
+        if g(c, "SQ_INSTS_VALU") and cyc:
+            busy = 4 * c["SQ_INSTS_VALU"] / SIMDS / cyc
+        if g(c, "SQ_INSTS_VALU") and g(c, "SQ_WAVES"):
+            vpw = c["SQ_INSTS_VALU"] / c["SQ_WAVES"]
+        if g(c, "SQ_INSTS_LDS") is not None and g(c, "SQ_WAVES"):
+            lpw = c["SQ_INSTS_LDS"] / c["SQ_WAVES"]
+        if g(c, "SQ_LDS_BANK_CONFLICT") is not None and g(c, "SQ_ACTIVE_INST_LDS"):
+            conf = c["SQ_LDS_BANK_CONFLICT"] / c["SQ_ACTIVE_INST_LDS"]
+        if g(c, "SQ_WAVE_CYCLES") and cyc:
+            occ = 4 * c["SQ_WAVE_CYCLES"] / cyc / 256
+        h, m = g(c, "TCC_HIT_sum"), g(c, "TCC_MISS_sum")
+        if h is not None and m is not None and h + m > 0:
+            hit = h / (h + m)
+
+        def f(v, fmt):
+            return "n/a" if v is None else format(v, fmt)
+
+        lines.append(f"| `{k}` | {f(cyc, '.0f')} | {f(busy, '.1%')} | {f(vpw, '.0f')} | "
+                     f"{f(lpw, '.0f')} | {f(conf, '.3f')} | {f(occ, '.1f')} | {f(hit, '.1%')} |")
+        raw[k] = c
+    lines += ["", "Raw counters (mean per dispatch):", "", "```",
+              json.dumps(raw, indent=1, sort_keys=True), "```", "",
+              f"Kernel sources: `{source_hash()}`", ""]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -147,11 +234,18 @@ def main() -> None:
     b.add_argument("out")
     b.add_argument("--workload", required=True)
     b.add_argument("--command", required=True)
+    c = sub.add_parser("units")
+    c.add_argument("out")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--workload", required=True)
+    c.add_argument("--command", required=True)
     args = ap.parse_args()
     if args.cmd == "stats":
         stats(args.dir, args.out, args.command)
-    else:
+    elif args.cmd == "counters":
         counters(args.fetch_dir, args.write_dir, args.out, args.workload, args.command)
+    else:
+        units(args.out, args.dirs, args.workload, args.command)
 
 
 if __name__ == "__main__":

@@ -402,9 +402,10 @@ FULL = [("voronoi450x375_n9_L60", "f32"), ("voronoi1242x375_n19_L128", "f32"),
 # End-to-end bound of the 16-bit cost forms against the oracle on the float32
 # costs, relative to max |V| like the float32 bar: the input rounding alone is
 # up to 2^-9 (bfloat16) / 2^-12 (float16) of each cost, and the filter is an
-# average of the costs with weights of either sign.  Provisional: twice the
-# worst single-cost rounding, until the first full-size measurement.
-E2E_BOUND = {"bf16": 2 * 2.0 ** -8, "f16": 2 * 2.0 ** -11}
+# average of the costs with weights of either sign.  Measured on the n = 19
+# workload: 1.18e-3 (bfloat16) and 1.19e-4 (float16), with either solve
+# precision; frozen at about 1.7 times that.
+E2E_BOUND = {"bf16": 2e-3, "f16": 2e-4}
 
 
 @pytest.mark.parametrize("name,stats", FULL, ids=[f"{n}-{s}" for n, s in FULL])
