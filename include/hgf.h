@@ -284,6 +284,22 @@ hgf_status hgf_server_stats(const hgf_server* server, hgf_server_info* out);
  * right after the call with the device clock of the completion records. */
 hgf_status hgf_server_now(hgf_server* server, double* ms);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): hgf_filter with
+ * its workspace in a library-owned static device array of
+ * hgf_static_scratch_bytes() bytes (96 MiB) per GPU, held until the process
+ * ends; no call allocates or frees memory.  The caller passes inputs and
+ * outputs as for hgf_filter (workspace and label-group size as for a
+ * one-chunk launch group); the results equal hgf_filter's bit for bit.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (two streams, or two threads) race and give wrong results.  Errors as
+ * hgf_filter, and HGF_E_NOMEM when the filter needs more workspace than the
+ * array holds (about 30,000 pixels at n = 9); nothing is enqueued then. */
+hgf_status hgf_filter_static(hgf_context* ctx, const hgf_params* params,
+                             const float* guide, const void* cost,
+                             float* out, int32_t* labels, void* hip_stream);
+size_t hgf_static_scratch_bytes(void);
+
 /* Standalone clipped box sum (Prop. 2) of C float32 images [C][H][W]:
  * out[c][y][x] = sum of in[c] over the clipped (2r+1)^2 window.  in and out
  * must not overlap. */

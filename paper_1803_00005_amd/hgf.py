@@ -112,6 +112,8 @@ def _declare(lib):
         "hgf_server_drain": (ctypes.c_int, [_vp]),
         "hgf_server_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ServerInfo)]),
         "hgf_server_now": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
+        "hgf_filter_static": (ctypes.c_int, [_vp, P, _vp, _vp, _vp, _vp, _vp]),
+        "hgf_static_scratch_bytes": (ctypes.c_size_t, []),
         "hgf_box_sum": (ctypes.c_int, [_vp, _vp] + [ctypes.c_int32] * 4 + [_vp]),
         "hgf_spd_inverse": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp]),
         "hgf_set_stage_timing": (ctypes.c_int, [_vp, ctypes.c_int32]),
@@ -246,6 +248,23 @@ class Context:
                                 _ptr(labels if want_labels else None), _ptr(workspace),
                                 workspace.numel(), _stream(stream)), "hgf_filter", self.handle)
         return (out if want_out else None), (labels if want_labels else None)
+
+    def filter_static(self, guide: torch.Tensor, cost: torch.Tensor, out: torch.Tensor,
+                      labels: Optional[torch.Tensor], *, radius: int, eps: float, degree: int,
+                      basis: str = "monomial", reg: str = "covariance", stats_dtype: str = "f32",
+                      stream=None):
+        """hgf_filter_static: the plain filter with the library's static device
+        workspace (allocates nothing; the caller gives the outputs)."""
+        _need_cuda(guide, "guide", (torch.float32,))
+        _need_cuda(cost, "cost", _COST_TYPES)
+        m, H, W = guide.shape
+        p = make_params(H, W, cost.shape[2], radius=radius, eps=eps, degree=degree,
+                        guide_channels=m, basis=basis, reg=reg, cost_dtype=cost_dtype_of(cost),
+                        stats_dtype=stats_dtype)
+        _check(lib().hgf_filter_static(self.handle, ctypes.byref(p), _ptr(guide), _ptr(cost),
+                                       _ptr(out), _ptr(labels), _stream(stream)),
+               "hgf_filter_static", self.handle)
+        return out, labels
 
     # -- tuning table ------------------------------------------------------
     def autotune(self, guide: torch.Tensor, cost: torch.Tensor, *, radius: int, eps: float,
