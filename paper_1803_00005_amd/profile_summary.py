@@ -46,7 +46,12 @@ def short_name(k: str) -> str:
         elif ch == "(" and depth == 0:
             k = k[:i]
             break
-    return k.split("hgf::")[-1] if "hgf::" in k else k[:60]
+    k = k.split("hgf::")[-1] if "hgf::" in k else k[:60]
+    # kernels in the library's inner namespaces keep their plain names
+    for ns in ("gk::", "sk::"):
+        if k.startswith(ns):
+            k = k[len(ns):]
+    return k
 
 
 def _find(d: str, suffix: str) -> list[str]:
