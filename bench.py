@@ -171,40 +171,51 @@ def measured_traffic(workload: str, stage: str):
 # CPU baseline: the FP64 oracle on a bounded sample, on the host cores
 # ----------------------------------------------------------------------------
 
-def _oracle_crop(args):
+def _oracle_band(job):
     from threadpoolctl import threadpool_limits
 
-    from oracle import hgf_oracle as O
-    guide, cost, w = args
+    from oracle import banded
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        O.filter_covariance(O.guidance(guide, w.degree, w.basis), cost, w.radius, w.eps)
+        banded.run_tile(job)
         return time.perf_counter() - t0
 
 
-def cpu_baseline(w: synth.Workload, guide, cost, target_s: float = 12.0):
+def cpu_baseline(w: synth.Workload, guide, cost, target_s: float = 12.0, tile: int = 128):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload:
+    output tiles of up to ``tile`` x ``tile`` pixels of the real image, each
+    computed exactly from its crop with a 2r halo on every side (the halo's
+    work counts against the oracle; only the tile's own px·labels count as
+    output)."""
     import multiprocessing as mp
 
-    cores = min(16, len(os.sched_getaffinity(0)))
-    W_ = w.width
-    rows = max(2 * w.radius + 2, 24)
-    # calibrate on one crop, then size the sample so that every core works ~target_s
-    t1 = _oracle_crop((guide[:, :rows], cost[:rows], w))
-    crops_per_core = max(1, int(target_s / max(t1, 1e-3)))
-    ncrops = cores * crops_per_core
-    starts = [(i * rows) % max(1, w.height - rows + 1) for i in range(ncrops)]
-    jobs = [(guide[:, s:s + rows], cost[s:s + rows], w) for s in starts]
-    ctx = mp.get_context("fork")
+    from oracle import banded
+    from oracle import hgf_oracle as O
+    cores = len(os.sched_getaffinity(0))
+    G = O.guidance(guide, w.degree, w.basis)
+    boxes = [(y0, min(w.height, y0 + tile), x0, min(w.width, x0 + tile))
+             for y0 in range(0, w.height, tile) for x0 in range(0, w.width, tile)]
+    # interior tiles first (a full-size tile with a full halo), then the rest
+    boxes.sort(key=lambda b: -((b[1] - b[0]) * (b[3] - b[2])))
+    job = lambda b: banded.tile_job(G, cost, w.radius, w.eps, b)
+    # calibrate on one tile, then size the sample so that every core works ~target_s
+    t1 = _oracle_band(job(boxes[0]))
+    ntiles = cores * max(1, int(target_s / max(t1, 1e-3)))
+    sample = [boxes[k % len(boxes)] for k in range(ntiles)]
+    ctx = mp.get_context("fork")   # before anything touches the GPU
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
-        pool.map(_oracle_crop, jobs, chunksize=1)
+        pool.map(_oracle_band, [job(b) for b in sample], chunksize=1)
     wall = time.perf_counter() - t0
-    pl = ncrops * rows * W_ * w.labels
+    pl = sum((b[1] - b[0]) * (b[3] - b[2]) for b in sample) * w.labels
+    a = boxes[0]
     return {"value": pl / wall / 1e6, "unit": UNIT, "cores": cores, "kind": "oracle",
-            "sample": f"{ncrops} crops of {W_}x{rows} px x {w.labels} labels (each filtered as "
-                      f"its own image, FP64 numpy, per-pixel LU), {cores} processes, "
-                      f"{wall:.1f} s wall; one crop on one core: {t1:.2f} s",
-            "single_core_value": rows * W_ * w.labels / t1 / 1e6}
+            "workload": w.name,
+            "sample": f"{ntiles} output tiles (up to {tile}x{tile} px) x {w.labels} labels of the "
+                      f"{w.name} image, each computed exactly from its crop with a "
+                      f"{2 * w.radius}-pixel halo (FP64 numpy, per-pixel LU), {cores} processes, "
+                      f"{wall:.1f} s wall; one tile on one core: {t1:.2f} s",
+            "single_core_value": (a[1] - a[0]) * (a[3] - a[2]) * w.labels / t1 / 1e6}
 
 
 # ----------------------------------------------------------------------------
@@ -336,6 +347,72 @@ def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True, autotune=True,
             "tuning": {["coef", "out", "moments"][r[0]]: r[6] for r in tuned}}
 
 
+def secondary_c1(ctx, reps=2000):
+    """The 64 x 64 colour workload (n = 3, 16 labels), which is launch-bound:
+    the latency of one filter call, back to back and alone (synchronised
+    after each call), and of the allocation-free call captured once in a
+    graph and replayed."""
+    import torch
+    w = synth.WORKLOADS["rgb64_n3_L16"]
+    guide, cost = synth.make_workload(w)
+    g = torch.from_numpy(guide).cuda()
+    c = torch.from_numpy(cost).cuda()
+    Z = torch.empty((w.height, w.width, w.labels), dtype=torch.float32, device="cuda")
+    lab = torch.empty((w.height, w.width), dtype=torch.int32, device="cuda")
+    from paper_1803_00005_amd import hgf
+    ws = torch.empty(hgf.workspace_size(hgf.make_params(
+        w.height, w.width, w.labels, radius=w.radius, eps=w.eps, degree=w.degree)),
+        dtype=torch.uint8, device="cuda")
+    f = lambda: ctx.filter(g, c, radius=w.radius, eps=w.eps, degree=w.degree, out=Z, labels=lab,
+                           workspace=ws)
+    for _ in range(20):
+        f()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    back_to_back = e0.elapsed_time(e1) / reps
+    t0 = time.perf_counter()
+    for _ in range(200):
+        f()
+        torch.cuda.synchronize()
+    alone = (time.perf_counter() - t0) / 200 * 1e3
+    rec = {"form": "latency", "workload": w.name, "pixel_labels": w.pixel_labels,
+           "ms_per_call_back_to_back": back_to_back, "ms_per_call_synchronised": alone,
+           "value": w.pixel_labels / back_to_back / 1e3, "unit": UNIT}
+    Zref, lref = Z.clone(), lab.clone()
+    try:
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            ctx.filter_static(g, c, Z, lab, radius=w.radius, eps=w.eps, degree=w.degree)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=st):
+            ctx.filter_static(g, c, Z, lab, radius=w.radius, eps=w.eps, degree=w.degree)
+        same = True
+        for _ in range(3):   # replays with eager work and synchronisation between them
+            Z.zero_()
+            graph.replay()
+            torch.cuda.synchronize()
+            same = same and torch.equal(Z, Zref) and torch.equal(lab, lref)
+        e0.record()
+        for _ in range(reps):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        rec["ms_per_graph_replay"] = e0.elapsed_time(e1) / reps
+        rec["graph_equals_eager_bitwise"] = bool(same)
+    except Exception as e:  # the plain-call figures stand on their own
+        rec["graph_error"] = repr(e)[:200]
+    say(f"c1 latency: {back_to_back * 1e3:.1f} us back to back, {alone * 1e3:.1f} us alone, "
+        f"graph {rec.get('ms_per_graph_replay', float('nan')) * 1e3:.1f} us")
+    return rec
+
+
 N19_FORMS = [("voronoi1242x375_n19_L128", "f32"), ("voronoi1242x375_n19_L128", "f64"),
              ("voronoi1242x375_n19_L128_bf16", "f64"), ("voronoi1242x375_n19_L128_f16", "f64")]
 
@@ -428,9 +505,19 @@ def secondary_batch(ctx, count, steps, warmup, check):
            "graph_equals_sequential_bitwise_first4": bool(equal),
            "data": "device-drawn (torch generator), same recipe"}
     if check:
+        # the two smallest images, and the image with the most coefficient
+        # workspace (the one most likely to run several launch groups)
         order = sorted(range(count), key=lambda i: specs[i].pixels)[:2]
-        rec["error"] = [dict(image=i, **sampled_error(specs[i], data[i][0], data[i][1],
-                                                      outs[i][0], outs[i][1], k=4))
+        big = max(range(count), key=lambda i: specs[i].pixel_labels * (specs[i].n + 1))
+        order.append(big)
+        groups = {}
+        for i in order:
+            w_ = specs[i]
+            per_chunk = w_.pixels * (w_.n + 1) * 64 * 4
+            groups[i] = -(-((w_.labels + 63) // 64) // max(1, (12 << 30) // per_chunk))
+        rec["error"] = [dict(image=i, launch_groups=groups[i],
+                             **sampled_error(specs[i], data[i][0], data[i][1], outs[i][0],
+                                             outs[i][1], k=4))
                         for i in order]
     del data, outs, seq_out, ws
     torch.cuda.empty_cache()
@@ -693,8 +780,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(synth.WORKLOADS))
-    ap.add_argument("--secondary", default="n19,batch,serve,inverse,gray",
-                    help="comma list of n19, batch, serve, inverse, gray, or 'none'")
+    ap.add_argument("--secondary", default="c1,n19,batch,serve,inverse,gray",
+                    help="comma list of c1, n19, batch, serve, inverse, gray, or 'none'")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -724,7 +811,7 @@ def main():
         sys.exit(2)
     secondary = [] if args.secondary == "none" else [x for x in args.secondary.split(",") if x]
     for x in secondary:
-        if x not in ("n19", "batch", "serve", "inverse", "gray"):
+        if x not in ("c1", "n19", "batch", "serve", "inverse", "gray"):
             ap.error(f"unknown secondary form {x!r}")
 
     w = synth.WORKLOADS[args.workload]
@@ -733,10 +820,14 @@ def main():
     guide, cost = synth.make_workload(w)
 
     # the host-core oracle runs before the GPU is touched (forked workers)
-    cpu = None
+    cpu = cpu_n19 = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, guide, cost)
         say(f"cpu baseline {cpu['value']:.3f} {UNIT} on {cpu['cores']} cores")
+        if "n19" in secondary:
+            w19 = synth.WORKLOADS["voronoi1242x375_n19_L128"]
+            cpu_n19 = cpu_baseline(w19, *synth.make_workload(w19))
+            say(f"cpu baseline n19 {cpu_n19['value']:.3f} {UNIT} on {cpu_n19['cores']} cores")
 
     import torch
 
@@ -775,9 +866,13 @@ def main():
     err = None if args.no_check else sampled_error(w, guide, cost, r["Z"], r["labels"])
 
     sec = []
+    if "c1" in secondary:
+        sec.append(secondary_c1(ctx))
     if "n19" in secondary:
         sec += secondary_n19(ctx, max(3, args.steps // 2), args.warmup, not args.no_check,
                              autotune=args.autotune)
+        if cpu_n19 is not None:
+            sec[-len(N19_FORMS)]["cpu_baseline"] = cpu_n19
     if "batch" in secondary:
         sec.append(secondary_batch(ctx, args.batch_count, args.batch_steps, 1,
                                    not args.no_check))

@@ -25,8 +25,22 @@ import numpy as np
 from . import hgf_oracle as O
 
 
-def _tile(args):
-    G, V, r, eps, mode, lc, (y0, y1, x0, x1), (cy, cx) = args
+def tile_job(G: np.ndarray, V: np.ndarray, r: int, eps: float, box, *, mode: str = "covariance",
+             label_chunk: int | None = None):
+    """The work of one output tile box = (y0, y1, x0, x1): its crop of G and V
+    with a 2r halo on every side (clipped to the image), for ``run_tile``.
+    ``label_chunk`` labels per solve (None: the oracle's own choice)."""
+    y0, y1, x0, x1 = box
+    H, W = V.shape[:2]
+    cy0, cy1 = max(0, y0 - 2 * r), min(H, y1 + 2 * r)
+    cx0, cx1 = max(0, x0 - 2 * r), min(W, x1 + 2 * r)
+    return (np.asarray(G[:, cy0:cy1, cx0:cx1], dtype=np.float64), np.asarray(V[cy0:cy1, cx0:cx1]),
+            r, eps, mode, label_chunk, (y0, y1, x0, x1), (cy0, cx0))
+
+
+def run_tile(job):
+    """((y0, x0), Z of the tile) for a job of ``tile_job``."""
+    G, V, r, eps, mode, lc, (y0, y1, x0, x1), (cy, cx) = job
     if mode == "covariance":
         Z = O.filter_covariance(G, V, r, eps, label_chunk=lc)
     elif mode == "ridge":
@@ -69,13 +83,8 @@ def filter_image(G: np.ndarray, V: np.ndarray, r: int, eps: float, *, mode: str 
         # about two tiles per worker, split along the longer side first
         ty = max(1, round((2 * workers * H / W) ** 0.5))
         tiles = (ty, max(1, -(-2 * workers // ty)))
-    jobs = []
-    for y0, y1 in _splits(H, tiles[0], r):
-        for x0, x1 in _splits(W, tiles[1], r):
-            cy0, cy1 = max(0, y0 - 2 * r), min(H, y1 + 2 * r)
-            cx0, cx1 = max(0, x0 - 2 * r), min(W, x1 + 2 * r)
-            jobs.append((G[:, cy0:cy1, cx0:cx1], np.asarray(V[cy0:cy1, cx0:cx1]), r, eps, mode,
-                         label_chunk, (y0, y1, x0, x1), (cy0, cx0)))
+    jobs = [tile_job(G, V, r, eps, (y0, y1, x0, x1), mode=mode, label_chunk=label_chunk)
+            for y0, y1 in _splits(H, tiles[0], r) for x0, x1 in _splits(W, tiles[1], r)]
     Z = np.empty((H, W, V.shape[2]), dtype=np.float64)
 
     def put(res):
@@ -84,10 +93,10 @@ def filter_image(G: np.ndarray, V: np.ndarray, r: int, eps: float, *, mode: str 
 
     if workers == 1 or len(jobs) == 1:
         for j in jobs:
-            put(_tile(j))
+            put(run_tile(j))
         return Z
     ctx = mp.get_context("spawn")
     with ctx.Pool(min(workers, len(jobs))) as pool:
-        for res in pool.imap_unordered(_tile, jobs):
+        for res in pool.imap_unordered(run_tile, jobs):
             put(res)
     return Z
