@@ -284,7 +284,8 @@ def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True, autotune=True,
         # by timing the candidates on these inputs (hgf_autotune)
         ctx.autotune(g_d, c_d, radius=w.radius, eps=w.eps, degree=w.degree, basis=w.basis,
                      stats_dtype=stats, stream=stream)
-    tuned = [r for r in ctx.tune_entries() if r[1] == w.n and r[2] == w.radius
+    mode = 1 if stats == "f64" else 0   # the solve form column of the tuning table
+    tuned = [r for r in ctx.tune_entries() if r[1] == w.n and r[2] == w.radius and r[3] == mode
              and r[4] == hgf.COST_DTYPES[w.cost_dtype]
              and r[5] == (w.pixels.bit_length() - 1)]
     for _ in range(warmup):

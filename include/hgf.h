@@ -211,7 +211,7 @@ hgf_status hgf_filter_batch(hgf_context* ctx, int32_t count, const hgf_params* p
  * Times every candidate block count of the guidance moment, coefficient and
  * output kernels on these inputs with HIP events (three passes of the whole
  * path each) and stores the fastest of each kernel in the context's table for
- * the class (kernel, n, radius, regularisation, cost dtype, floor(log2 H W)).
+ * the class (kernel, n, radius, solve form, cost dtype, floor(log2 H W)).
  * Later calls of that class use it.  Synchronises hip_stream.  `out` may be
  * NULL; when given it receives valid filtered costs.  Workspace as hgf_filter.
  * A table entry changes the band boundaries of the float32 running sums, so
@@ -221,8 +221,9 @@ hgf_status hgf_autotune(hgf_context* ctx, const hgf_params* params,
                         void* workspace, size_t workspace_bytes, void* hip_stream);
 
 /* The tuning table as rows of 7 int32 (kernel 0=coefficients 1=output
- * 2=guidance moment sums, n, radius, reg, cost is bf16, size class, target
- * blocks).  Writes at most
+ * 2=guidance moment sums, n, radius, solve form 0=covariance with float32
+ * solve 1=covariance with float64 solve 2=ridge, cost hgf_dtype, size class,
+ * target blocks).  Writes at most
  * max_rows rows (rows may be NULL) and the total row count to *count. */
 hgf_status hgf_tune_entries(const hgf_context* ctx, int32_t* rows, int32_t max_rows,
                             int32_t* count);

@@ -203,7 +203,7 @@ int size_class(int P) {
 }
 
 TuneKey tune_key(int kernel, const Plan& pl) {
-  return TuneKey(kernel, pl.n, pl.R, pl.reg, pl.cost_type, size_class(pl.P));
+  return TuneKey(kernel, pl.n, pl.R, pl.mode, pl.cost_type, size_class(pl.P));
 }
 
 const std::vector<int>& tune_candidates() {

@@ -72,7 +72,7 @@ Plan make_plan(const hgf_params* p, const MonoTable& table, int chunks_ws,
 
 // ---------------------------------------------------------------------------
 // tuning: target block counts of the strip kernels, chosen by the autotuner
-// per (kernel, n, radius, regularisation, cost dtype, image size class)
+// per (kernel, n, radius, solve mode, cost dtype, image size class)
 // ---------------------------------------------------------------------------
 enum TuneKernel { kTuneCoef = 0, kTuneOut = 1, kTuneMoments = 2 };
 using TuneKey = std::tuple<int, int, int, int, int, int>;

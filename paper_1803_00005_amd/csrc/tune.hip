@@ -156,7 +156,7 @@ hgf_status hgf_tune_save(const hgf_context* ctx, const char* path) {
   if (ctx == nullptr || path == nullptr) return fail(HGF_E_INVALID, "context or path is NULL");
   FILE* f = std::fopen(path, "w");
   if (f == nullptr) return fail(HGF_E_INVALID, "cannot write %s", path);
-  std::fprintf(f, "# kernel n radius reg cost_dtype size_class target_blocks\n");
+  std::fprintf(f, "# kernel n radius solve_form cost_dtype size_class target_blocks\n");
   for (const auto& kv : ctx->tune)
     std::fprintf(f, "%d %d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
                  std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first),

@@ -22,7 +22,8 @@ def _shapes(quick: bool):
     from . import synth
     named = [synth.WORKLOADS[k] for k in ("rgb64_n3_L16", "voronoi450x375_n9_L60",
                                           "voronoi1242x375_n19_L128",
-                                          "voronoi1242x375_n19_L128_bf16")]
+                                          "voronoi1242x375_n19_L128_bf16",
+                                          "voronoi1242x375_n19_L128_f16")]
     if quick:
         return named
     out = []
@@ -45,6 +46,8 @@ def _shapes(quick: bool):
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--base", default=DEFAULT_TABLE,
+                    help="table to start from (its other entries are kept); 'none' starts empty")
     ap.add_argument("--quick", action="store_true", help="named workloads only")
     args = ap.parse_args()
     import torch
@@ -52,10 +55,16 @@ def main() -> None:
     from . import hgf, synth
     dev = torch.device("cuda", 0)
     ctx = hgf.Context(0)
+    if args.base != "none" and os.path.exists(args.base):
+        ctx.tune_load(args.base)
     for w in _shapes(args.quick):
         g, c = synth.make_workload_device(w, dev)
-        ctx.autotune(g, c, radius=w.radius, eps=w.eps, degree=w.degree, basis=w.basis)
-        torch.cuda.synchronize()
+        # the n = 19 workloads are also run with the float64 solve (its own
+        # coefficient kernel)
+        for stats in (("f32", "f64") if w.n >= 10 else ("f32",)):
+            ctx.autotune(g, c, radius=w.radius, eps=w.eps, degree=w.degree, basis=w.basis,
+                         stats_dtype=stats)
+            torch.cuda.synchronize()
         rows = [r for r in ctx.tune_entries() if r[1] == w.n and r[2] == w.radius]
         print(f"[tune] {w.name}: {len(rows)} entries", flush=True)
         del g, c

@@ -172,6 +172,11 @@ RIDGE_CASES = [
     W("ridge_n9_L1", height=40, width=90, degree=2, labels=1, radius=4, eps=0.05, seed=37),
     W("ridge_n12_r5", height=36, width=58, basis="power", degree=4, labels=30, radius=5,
       eps=0.05, seed=38),
+    # the gray sweep's other one-label kernels (n = 3 and 7, the setting of Tables 1-2)
+    W("ridge_gray_power_n3_L1", height=90, width=130, guide_channels=1, basis="power",
+      degree=3, labels=1, radius=7, eps=0.05, seed=53),
+    W("ridge_gray_power_n7_L1", height=75, width=160, guide_channels=1, basis="power",
+      degree=7, labels=1, radius=7, eps=0.05, seed=54),
     W("ridge_r0_n3", height=17, width=21, degree=1, labels=6, radius=0, eps=0.05, seed=39),
 ]
 
