@@ -643,9 +643,33 @@ def secondary_serve(ctx, requests, pool_size, rate, slots, arena_gb, low_rate, l
                            degree=w.degree)
         torch.cuda.synchronize()
         same = same and torch.equal(z, pool.outputs[j][0]) and torch.equal(lb, pool.outputs[j][1])
+    # the plain path on the same requests (after the check above, which reads
+    # the served outputs): every pool entry once, back to back through
+    # hgf_filter on one stream (no queueing, no overlap)
+    from paper_1803_00005_amd import hgf
+    wsz = max(hgf.workspace_size(hgf.make_params(
+        w.height, w.width, w.labels, radius=w.radius, eps=w.eps, degree=w.degree,
+        cost_dtype=w.cost_dtype)) for w in pool.specs)
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for j, w in enumerate(pool.specs):
+        ctx.filter(pool.inputs[j][0], pool.inputs[j][1], radius=w.radius, eps=w.eps,
+                   degree=w.degree, out=pool.outputs[j][0], labels=pool.outputs[j][1],
+                   workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    plain_value = sum(w.pixel_labels for w in pool.specs) / plain_ms / 1e3
+    del ws
+    say(f"serve: plain path on the pool {plain_value:.0f} {UNIT}")
     rec = {"form": "serve", "workload": f"poisson{int(rate)}rps_{requests}req",
            "distinct_inputs": pool_size, "slots": slots, "arena_gb": arena_gb,
            **main, "below_capacity": low, "served_equals_alone_bitwise": bool(same),
+           "plain_path": {"value": plain_value, "unit": UNIT, "ms": plain_ms,
+                          "what": f"the {pool_size} pool requests through hgf_filter back to "
+                                  "back on one stream"},
            "data": "device-drawn (torch generator), same recipe; request k of a stream uses the "
                    f"shape and inputs of entry k mod {pool_size} of a pool drawn from the "
                    "serving mix"}
