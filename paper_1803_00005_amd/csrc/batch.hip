@@ -136,6 +136,8 @@ static hgf_status filter_batch(hgf_context* ctx, int32_t count, const hgf_params
 
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (ctx->graph == nullptr || ctx->graph->signature != sig) {
+    // the previous graph may still be replaying on some stream
+    if (ctx->graph != nullptr) wait_used(ctx->batch_done);
     ctx->graph.reset();
     auto g = std::make_unique<hgf_batch_graph>();
     g->signature = sig;

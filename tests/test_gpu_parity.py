@@ -460,6 +460,36 @@ def test_full_size_two_phase_equals_plain(ctx, name):
     np.testing.assert_array_equal(lab.cpu().numpy(), labp)
 
 
+def _sample_points(H, Wd, k, seed):
+    rng = np.random.default_rng(seed)
+    pts = {(0, 0), (0, Wd - 1), (H - 1, 0), (H - 1, Wd - 1), (H // 2, Wd // 2), (5, Wd - 3),
+           (H - 4, 7)}
+    while len(pts) < k:
+        pts.add((int(rng.integers(0, H)), int(rng.integers(0, Wd))))
+    return sorted(pts)
+
+
+def test_largest_image_sampled(ctx):
+    """The largest image of the batched and serving mixes: 1920 x 1080, n = 19,
+    256 labels, r = 9 (about 10 GB of coefficient workspace per 64-label
+    chunk, so the call runs its labels in several launch groups).  Every
+    output is checked by properties that hold at any size; 24 pixels against
+    the oracle, each computed exactly from its (4r+1)^2 neighbourhood."""
+    w = W("largest_n19_L256", height=1080, width=1920, regions=40, labels=256, radius=9,
+          eps=1e-3, degree=3, seed=61)
+    say(f"largest image {w.height}x{w.width} n={w.n} L={w.labels}")
+    guide, cost = synth.make_workload(w)
+    per_chunk = w.pixels * (w.n + 1) * 64 * 4
+    assert (12 << 30) // per_chunk < (w.labels + 63) // 64   # several launch groups
+    Z, lab = gpu_filter(ctx, guide, cost, w)
+    assert np.isfinite(Z).all()
+    assert np.array_equal(lab, np.argmin(Z.astype(np.float32), axis=2))
+    pts = _sample_points(w.height, w.width, 24, 98)
+    Zo = O.filter_points(O.guidance(guide, w.degree, w.basis), cost, w.radius, w.eps, pts)
+    idx = tuple(np.array(pts).T)
+    check(Z[idx], lab[idx], Zo, cost, w.name + " sampled")
+
+
 LG = W("launch_groups_n9", height=61, width=77, regions=9, labels=200, radius=4, degree=2,
        seed=60)
 
