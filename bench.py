@@ -150,6 +150,11 @@ def roofline_of(name, model, ms_per_launch, traffic):
             "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
 
 
+def profile_name(w: synth.Workload, stats: str = "f32") -> str:
+    """Name of a workload's profile summaries (the float64 solve has its own)."""
+    return w.name + ("_f64" if stats == "f64" else "")
+
+
 def measured_traffic(workload: str, stage: str):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
     were taken on the current sources of that kernel; else None."""
@@ -342,7 +347,7 @@ def run_plain(ctx, w, g_d, c_d, steps, warmup, stage_timing=True, autotune=True,
                   "peak": st["peak"], "frac": st["frac"]}
         roof = method_roofline(w, KERNEL_NAMES.get(dom["stage"], dom["stage"]),
                                w.pixel_labels / per_step, dom["ms_per_launch"], staged,
-                               measured_traffic(w.name, dom["stage"]), ms)
+                               measured_traffic(profile_name(w, stats), dom["stage"]), ms)
     return {"ms": ms, "ms_stage_timed": ms_staged, "stages": rows, "roofline": roof, "Z": Z,
             "labels": lab,
             "tuning": {["coef", "out", "moments"][r[0]]: r[6] for r in tuned}}
@@ -805,6 +810,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--stats-dtype", default="f32", choices=("f32", "f64"),
+                    help="precision of the per-pixel solve of the timed workload")
     ap.add_argument("--secondary", default="c1,n19,batch,serve,inverse,gray",
                     help="comma list of c1, n19, batch, serve, inverse, gray, or 'none'")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -884,7 +891,7 @@ def main():
 
     t0 = time.perf_counter()
     r = run_plain(ctx, w, g_d, c_d, args.steps, args.warmup, not args.no_stage_timing,
-                  autotune=args.autotune)
+                  autotune=args.autotune, stats=args.stats_dtype)
     ms = r["ms"]
     say(f"timed {args.steps} steps: {ms:.4f} ms/step (wall {time.perf_counter() - t0:.3f} s)")
     value = w.pixel_labels / (ms * 1e-3) / 1e6
@@ -917,6 +924,7 @@ def main():
         "config": {"workload": w.name, "height": w.height, "width": w.width, "labels": w.labels,
                    "n": w.n, "degree": w.degree, "basis": w.basis, "radius": w.radius,
                    "eps": w.eps, "cost_dtype": w.cost_dtype, "reg": "covariance",
+                   "stats_dtype": args.stats_dtype,
                    "pixel_labels_per_step": w.pixel_labels},
         "roofline": r["roofline"], "cpu_baseline": cpu, "error": err, "stages": r["stages"],
         "ms_per_step_stage_timed": r["ms_stage_timed"],
