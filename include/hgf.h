@@ -295,7 +295,10 @@ hgf_status hgf_server_now(hgf_server* server, double* ms);
  * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
  * (two streams, or two threads) race and give wrong results.  Errors as
  * hgf_filter, and HGF_E_NOMEM when the filter needs more workspace than the
- * array holds (about 30,000 pixels at n = 9); nothing is enqueued then. */
+ * array holds (about 30,000 pixels at n = 9); nothing is enqueued then.
+ * With stage timing switched on (hgf_set_stage_timing) the context records
+ * timing events, creating them on first use; leave it off where nothing may
+ * be created. */
 hgf_status hgf_filter_static(hgf_context* ctx, const hgf_params* params,
                              const float* guide, const void* cost,
                              float* out, int32_t* labels, void* hip_stream);

@@ -20,9 +20,11 @@ namespace hgf {
 // in target_blocks with every chunk of the volume in one launch (never more:
 // a grid slightly larger than a multiple of the resident workgroup slots
 // leaves a nearly empty last round).  Each band restarts the vertical running
-// sums (2R + 1 rows of set-up), so bands are at least kMinBand rows; at most
-// kMaxBand rows bound the float32 drift of the running sums.
-constexpr int kMinBand = 4;
+// sums (2R + 1 rows of set-up), which the tuned targets keep in proportion
+// for large images; small images take bands down to one row, so that their
+// latency-bound strips run as more, shorter blocks.  At most kMaxBand rows
+// bound the float32 drift of the running sums.
+constexpr int kMinBand = 1;
 constexpr int kMaxBand = 64;
 
 StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int chunks_total,
