@@ -250,9 +250,15 @@ hgf_status hgf_tune_load(hgf_context* ctx, const char* path);
  *                      returns up to max_done completion records, oldest
  *                      first.  Outputs of a completed request are ready.
  *   hgf_server_drain   blocks until every submitted request has completed.
+ * Once hgf_server_submit has set *id the request is queued, even when the
+ * call returns an error: submit, poll and drain also launch waiting
+ * requests and return the first launch error among them, and poll and
+ * drain return the first device error of the requests they retire; every
+ * failed request's completion record carries its own status.
  * Completion times are on the device clock in milliseconds since the server
  * was created.  A request computes exactly what hgf_filter computes for the
- * same parameters and tuning table. */
+ * same parameters and tuning table.  A server is used from one host thread
+ * at a time. */
 typedef struct hgf_server hgf_server;
 typedef struct {
   int64_t id;

@@ -29,22 +29,24 @@ __device__ __forceinline__ double monomial(const MonoTable& t, int k, const floa
 // ---------------------------------------------------------------------------
 constexpr int kShiftGrid = kShiftRows;  // sample grid: at most 16 x 16 pixels
 
-// One block of kShiftRows x kShiftRows threads, one sample each: each wave
-// sums its samples over the lanes by a fixed xor butterfly (which leaves the
-// same bits in every lane; all channels in lockstep, so the shuffle
-// latencies overlap), and the waves' sums are added in wave order.
+// One block of kShiftRows x kShiftRows threads, one sample each.  The
+// samples' monomials go to LDS; then kShiftParts threads per channel each add
+// a quarter of the samples in index order, and one thread per channel adds
+// the quarters in order (a fixed order: the shift is deterministic).
 constexpr int kShiftThreads = kShiftGrid * kShiftGrid;
-constexpr int kShiftWaves = kShiftThreads / 64;
+constexpr int kShiftParts = 4;
+constexpr int kShiftPart = kShiftThreads / kShiftParts;
+static_assert(kMaxD * kShiftParts <= kShiftThreads, "one thread per channel part");
 
 __global__ __launch_bounds__(kShiftThreads) void guide_shift_kernel(
     const float* __restrict__ I, int H, int W, MonoTable t, int centre,
     double* __restrict__ shift) {
-  __shared__ double wsum[kShiftWaves * kMaxD];
+  __shared__ double sv[kMaxD * kShiftThreads];
+  __shared__ double part[kMaxD * kShiftParts];
   const int sy = (H + kShiftGrid - 1) / kShiftGrid, sx = (W + kShiftGrid - 1) / kShiftGrid;
   const int ny = (H + sy - 1) / sy, nx = (W + sx - 1) / sx;
   const size_t P = static_cast<size_t>(H) * W;
   const int tid = static_cast<int>(threadIdx.x);
-  const int lane = tid & 63, wv = tid >> 6;
   const int gy = tid / kShiftGrid, gx = tid % kShiftGrid;
   const bool in = gy < ny && gx < nx;
   float iv[4] = {0.f, 0.f, 0.f, 0.f};
@@ -52,25 +54,20 @@ __global__ __launch_bounds__(kShiftThreads) void guide_shift_kernel(
     const size_t p = static_cast<size_t>(gy * sy) * W + gx * sx;
     for (int c = 0; c < t.m; ++c) iv[c] = I[static_cast<size_t>(c) * P + p];
   }
-  double v[kMaxD];
-#pragma unroll
-  for (int k = 0; k < kMaxD; ++k) v[k] = (k < t.n && in) ? monomial(t, k, iv) : 0.0;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-    for (int k = 0; k < kMaxD; ++k) v[k] += __shfl_xor(v[k], off, 64);
-  if (lane < kMaxD) {
-    double mine = 0.0;
-#pragma unroll
-    for (int k = 0; k < kMaxD; ++k)
-      if (k == lane) mine = v[k];
-    wsum[wv * kMaxD + lane] = mine;
+  for (int k = 0; k < t.n; ++k) sv[k * kShiftThreads + tid] = in ? monomial(t, k, iv) : 0.0;
+  __syncthreads();
+  const int k = tid / kShiftParts, q = tid % kShiftParts;
+  if (k < t.n) {
+    const double* __restrict__ src = sv + k * kShiftThreads + q * kShiftPart;
+    double acc = 0.0;
+    for (int i = 0; i < kShiftPart; ++i) acc += src[i];
+    part[k * kShiftParts + q] = acc;
   }
   __syncthreads();
   if (tid < t.n) {
     double tot = 0.0;
 #pragma unroll
-    for (int w = 0; w < kShiftWaves; ++w) tot += wsum[w * kMaxD + tid];
+    for (int j = 0; j < kShiftParts; ++j) tot += part[tid * kShiftParts + j];
     shift[tid] = centre ? tot / static_cast<double>(ny * nx) : 0.0;
   }
 }

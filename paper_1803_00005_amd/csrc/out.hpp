@@ -128,11 +128,12 @@ __device__ __forceinline__ void out_strip(const float* __restrict__ wsc,
   // boundaries), so the start-up rows are shared through L2 rather than read
   // twice from HBM.
   const int ystart = up ? y1 - 1 : y0;
-  // initial window: rows ystart - R .. ystart + R (two at a time when paired)
+  // initial window: rows ystart - R .. ystart + R (two at a time with one
+  // channel per wave)
   {
     const int ra = max(0, ystart - R), rb = min(H - 1, ystart + R);
     int yy = ra;
-    for (; PAIR && yy + 1 <= rb; yy += 2)
+    for (; (PAIR || CPW == 1) && yy + 1 <= rb; yy += 2)
       out_vrow<1, 1, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, yy, yy + 1, launder(), W, wv, lane);
     for (; yy <= rb; ++yy) out_vrow<1, 0, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, yy, 0, launder(), W, wv, lane);
   }
