@@ -218,6 +218,12 @@ int tuned_target(hgf_context* ctx, int kernel, const Plan& pl) {
     auto it = ctx->tune.find(tune_key(kernel, pl));
     if (it != ctx->tune.end()) return it->second;
   }
+  // untuned: output blocks of fewer than eight waves (few channels) need
+  // more blocks to keep enough loads in flight
+  if (kernel == kTuneOut) {
+    const int cpw = out_channels_per_wave(pl.n);
+    if ((pl.n + 1 + cpw - 1) / cpw < 8) return 2 * kDefaultTarget;
+  }
   return kDefaultTarget;
 }
 

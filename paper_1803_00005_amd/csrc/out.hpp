@@ -26,12 +26,15 @@
 #include "hgf_launch.hpp"
 
 namespace hgf {
-// LDS for the per-wave partial dot products (float64) of one column chunk
-constexpr int kOutPartBytes = 120 * 1024;
+// LDS for the per-wave partial dot products (float64) of one column chunk:
+// 12 KB per wave, at most 120 KB.  Blocks of few waves (few channels) then
+// leave room for more blocks per CU, so every layout keeps about ten or more
+// waves per CU resident.
+constexpr int out_part_bytes(int nw) { return nw * 12 * 1024 < 120 * 1024 ? nw * 12 * 1024 : 120 * 1024; }
 
 template <int NW, int SOUT>
 constexpr int out_column_chunk() {
-  int oc = kOutPartBytes / (NW * 64 * 8);
+  int oc = out_part_bytes(NW) / (NW * 64 * 8);
   if (oc > SOUT) oc = SOUT;
   if (oc < 1) oc = 1;
   const int ncb = (SOUT + oc - 1) / oc;
@@ -128,13 +131,15 @@ __device__ __forceinline__ void out_strip(const float* __restrict__ wsc,
   // boundaries), so the start-up rows are shared through L2 rather than read
   // twice from HBM.
   const int ystart = up ? y1 - 1 : y0;
-  // initial window: rows ystart - R .. ystart + R (two at a time with one
-  // channel per wave)
+  // initial window: rows ystart - R .. ystart + R; with one channel per wave
+  // two rows at a time in groups of 32 columns (small images are mostly
+  // start-up, and each group is one memory round trip)
   {
+    constexpr int GI = CPW == 1 ? 32 : GRP;
     const int ra = max(0, ystart - R), rb = min(H - 1, ystart + R);
     int yy = ra;
     for (; (PAIR || CPW == 1) && yy + 1 <= rb; yy += 2)
-      out_vrow<1, 1, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, yy, yy + 1, launder(), W, wv, lane);
+      out_vrow<1, 1, CHECK, CPW, NCH, SIN, GI>(vs, wsc, yy, yy + 1, launder(), W, wv, lane);
     for (; yy <= rb; ++yy) out_vrow<1, 0, CHECK, CPW, NCH, SIN, GRP>(vs, wsc, yy, 0, launder(), W, wv, lane);
   }
   const int dir = up ? -1 : 1;

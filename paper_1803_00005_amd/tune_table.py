@@ -4,7 +4,7 @@
 
 Runs hgf_autotune on synthetic inputs of each size class the benchmarks use
 (the named workloads, and images of 2^16 .. 2^21 pixels for every channel
-count and radius of the batched and serving mixes) and saves the table with
+count and radius of the batched and serving mixes, and gray guidance) and saves the table with
 hgf_tune_save.  A context loads it with hgf_tune_load (Context.tune_load).
 Needs a GPU.
 """
@@ -39,6 +39,12 @@ def _shapes(quick: bool):
                         name=f"class{cls}_d{degree}_r{radius}_{dt}", height=H, width=W,
                         regions=40, labels=64, radius=radius, eps=eps, degree=degree,
                         disparity="planar", seed=7000 + cls, cost_dtype=dt))
+        # gray guidance, n = 1
+        for radius in (4, 9):
+            out.append(synth.Workload(
+                name=f"class{cls}_gray_r{radius}_f32", height=H, width=W, regions=40,
+                labels=64, radius=radius, eps=1e-4, degree=1, disparity="planar",
+                seed=7100 + cls, guide_channels=1))
     # the named workloads last, so their own measurements decide their classes
     return out + named
 
