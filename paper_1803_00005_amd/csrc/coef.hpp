@@ -571,7 +571,7 @@ hipError_t coef_launch_t(const CoefLaunch& a, hipStream_t s) {
   constexpr int NCH = NG + 1;
   constexpr int CPW = NCH > 10 ? 2 : 1;
   constexpr int NWB = coef_block_waves((NCH + CPW - 1) / CPW);
-  constexpr int SIN = coef_strip_width(NG);
+  constexpr int SIN = coef_strip_width(NG, R);
   const StripGrid& g = a.grid;
   const unsigned blocks = static_cast<unsigned>(g.strips * g.bands * g.chunks);
   hipLaunchKernelGGL((coef_kernel<R, CPW, NG, MODE, TIN, SIN>), dim3(blocks), dim3(NWB * 64), 0,

@@ -413,7 +413,7 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
     ca.R = pl.R;
     ca.mode = pl.mode;
     ca.label_count = lc;
-    ca.grid = strip_grid_w(pl.H, pl.W, pl.R, coef_strip_width(pl.n), chunks, pl.chunks_total,
+    ca.grid = strip_grid_w(pl.H, pl.W, pl.R, coef_strip_width(pl.n, pl.R), chunks, pl.chunks_total,
                            coef_target);
     {
       Stage st(ctx, 4, s);
@@ -432,7 +432,7 @@ hgf_status run_labels(hgf_context* ctx, const Plan& pl, const void* cost, int co
     oa.W = pl.W;
     oa.R = pl.R;
     oa.label_count = lc;
-    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, out_strip_width(pl.n), chunks, pl.chunks_total,
+    oa.grid = strip_grid_w(pl.H, pl.W, pl.R, out_strip_width(pl.n, pl.R), chunks, pl.chunks_total,
                            out_target);
     {
       Stage st(ctx, 5, s);

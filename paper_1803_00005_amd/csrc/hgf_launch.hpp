@@ -28,12 +28,23 @@ StripGrid strip_grid_w(int H, int W, int R, int sin, int chunks, int chunks_tota
 
 // State columns per strip of the coefficient kernel: up to n = 9 one channel
 // per wave and 64 columns; above, two channels per wave and a narrower strip
-// so that ten waves fit the register file.
-constexpr int coef_strip_width(int n) { return n + 1 > 10 ? 38 : (n + 1 == 10 ? 62 : 64); }
+// so that ten waves fit the register file.  With at most three guidance
+// channels and a radius of at most 4, 32 output columns (2r + 32 state
+// columns): the smaller register and LDS footprint lets two blocks share a
+// CU, which these short solves need more than the wider strip's smaller
+// halo share (measured faster at r = 4, slower at r = 9).
+constexpr int coef_strip_width(int n, int r) {
+  return n + 1 > 10 ? 38 : (n + 1 == 10 ? 62 : (n + 1 <= 4 && r <= 4 ? 2 * r + 32 : 64));
+}
 // Output kernel: channels per wave (ten waves at most) and state columns per
-// strip for n guidance channels (two channels per wave leave room for 48).
+// strip for n guidance channels (two channels per wave leave room for 48;
+// with at most three guidance channels and a radius of at most 4, 2r + 32
+// state columns as in the coefficient kernel, whose smaller register
+// footprint keeps more waves resident).
 constexpr int out_channels_per_wave(int n) { return n + 1 > 10 ? 2 : 1; }
-constexpr int out_strip_width(int n) { return out_channels_per_wave(n) > 1 ? 48 : 64; }
+constexpr int out_strip_width(int n, int r) {
+  return out_channels_per_wave(n) > 1 ? 48 : (n + 1 <= 4 && r <= 4 ? 2 * r + 32 : 64);
+}
 
 // Radii with compiled strip kernels.
 bool radius_supported(int R);

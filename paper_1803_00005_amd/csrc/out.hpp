@@ -288,7 +288,7 @@ __global__ __launch_bounds__(640) void out_kernel(
 template <int R, int NG>
 hipError_t out_launch_t(const OutLaunch& a, hipStream_t s) {
   constexpr int CPW = out_channels_per_wave(NG);
-  constexpr int SIN = out_strip_width(NG);
+  constexpr int SIN = out_strip_width(NG, R);
   constexpr int GRP = 8;
   // one channel per wave and eight or nine channels: the entering and the
   // leaving row are loaded together; otherwise one row at a time (there the
