@@ -130,6 +130,13 @@ CASES = [
       cost_dtype="f16", seed=51),
     W("one_label_f16", height=27, width=33, labels=1, radius=3, degree=2, cost_dtype="f16",
       seed=52),
+    # the narrow strips of n <= 3 at r <= 4: several strips with a ragged last
+    # one, two label chunks, 16-bit costs
+    W("n3_r1_bf16_two_chunks", height=61, width=150, labels=70, radius=1, degree=1,
+      cost_dtype="bf16", seed=53),
+    W("n3_r4_f16_ragged", height=45, width=170, labels=20, radius=4, degree=1, cost_dtype="f16",
+      seed=54),
+    W("n1_gray_r3_ragged", height=70, width=131, guide_channels=1, labels=33, radius=3, seed=55),
 ]
 
 
