@@ -97,7 +97,7 @@ def generate() -> list[str]:
             f'#include "guide_kernels.hpp"\n'
             f"namespace hgf {{\n"
             f"template hipError_t moments_n<{n}>(const double*, int, int, int, int, double*,\n"
-            f"                                  hipStream_t);\n"
+            f"                                  double, int, double*, void*, int*, hipStream_t);\n"
             f"template hipError_t invert_n<{n}>(const double*, int, int, int, double, int,\n"
             f"                                 double*, void*, hipStream_t);\n"
             f"}}\n")

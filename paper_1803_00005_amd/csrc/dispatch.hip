@@ -17,8 +17,8 @@ hipError_t coef_launch_nr(const CoefLaunch& a, hipStream_t s);
 template <int NG>
 hipError_t out_launch_n(const OutLaunch& a, hipStream_t s);
 template <int NG>
-hipError_t moments_n(const double* g64, int H, int W, int R, int target, double* S,
-                     hipStream_t s);
+hipError_t moments_n(const double* g64, int H, int W, int R, int target, double* S, double eps,
+                     int mode, double* mu, void* minv, int* fused, hipStream_t s);
 template <int NG>
 hipError_t invert_n(const double* S, int H, int W, int R, double eps, int mode, double* mu,
                     void* minv, hipStream_t s);
@@ -81,9 +81,11 @@ hipError_t launch_out(const OutLaunch& a, hipStream_t s) {
 }
 
 hipError_t launch_moments(const double* g64, int n, int H, int W, int R, int target, double* S,
+                          double eps, int mode, double* mu, void* minv, int* fused,
                           hipStream_t s) {
+  *fused = 0;
   if (!config_supported(n, R)) return hipErrorNotSupported;
-  return kMoments[n - 1](g64, H, W, R, target, S, s);
+  return kMoments[n - 1](g64, H, W, R, target, S, eps, mode, mu, minv, fused, s);
 }
 
 hipError_t launch_invert(const double* S, int n, int H, int W, int R, double eps, int mode,

@@ -47,10 +47,78 @@ __device__ __forceinline__ void add_moments(double (&vs)[KW], const double (&g)[
   }
 }
 
-template <int R, int NG, int KW>
+// ---------------------------------------------------------------------------
+// a3 for one pixel: from its window sums s (the K moments), its window count
+// Np and the regulariser, the window means mu (covariance form; zero in the
+// ridge form) and the packed inverse M of the regularised D x D system, by
+// the bordering recursion described with invert_kernel below.  Used by the
+// inverse kernels and by the moment kernel with the inverse fused in.
+// ---------------------------------------------------------------------------
+template <int D, int MODE>
+__device__ __forceinline__ void pixel_inverse(const double* __restrict__ s, double Np, double eps,
+                                              double (&mu)[MODE == kSolveRidge ? D - 1 : D],
+                                              double (&M)[D * (D + 1) / 2]) {
+  constexpr bool RIDGE = MODE == kSolveRidge;
+  constexpr int NG = RIDGE ? D - 1 : D;
+  const double invN = 1.0 / Np;
+#pragma unroll
+  for (int i = 0; i < NG; ++i) mu[i] = RIDGE ? 0.0 : s[i] * invN;
+
+  // entry (i, j), i <= j, of the regularised system
+  auto A = [&](int i, int j) -> double {
+    if (!RIDGE) {
+      return fma(s[NG + packed_index(i, j, NG)], invN, -mu[i] * mu[j]) + (i == j ? eps : 0.0);
+    }
+    if (i == 0) return (j == 0) ? Np + eps : s[j - 1];
+    return s[NG + packed_index(i - 1, j - 1, NG)] + (i == j ? eps : 0.0);
+  };
+
+  M[0] = 1.0 / A(0, 0);
+#pragma unroll
+  for (int kap = 1; kap < D; ++kap) {
+    double g[D];
+    double u[D];
+#pragma unroll
+    for (int i = 0; i < kap; ++i) g[i] = A(i, kap);
+#pragma unroll
+    for (int i = 0; i < kap; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < kap; ++j)
+        acc = fma(M[i <= j ? packed_index(i, j, D) : packed_index(j, i, D)], g[j], acc);
+      u[i] = acc;
+    }
+    double schur = A(kap, kap);
+#pragma unroll
+    for (int i = 0; i < kap; ++i) schur = fma(-g[i], u[i], schur);
+    const double inv = 1.0 / schur;
+#pragma unroll
+    for (int i = 0; i < kap; ++i) {
+      const double ui = u[i] * inv;
+#pragma unroll
+      for (int j = i; j < kap; ++j) M[packed_index(i, j, D)] = fma(ui, u[j], M[packed_index(i, j, D)]);
+      M[packed_index(i, kap, D)] = -ui;
+    }
+    M[packed_index(kap, kap, D)] = inv;
+  }
+}
+
+// Channel counts whose moment kernel also computes the inverse (the inverse's
+// registers are few, so the window sums need not go through HBM).
+constexpr int kFuseMaxN = 4;
+
+// The system size of a solve mode for n guidance channels.
+constexpr int system_size(int mode, int n) { return mode == kSolveRidge ? n + 1 : n; }
+
+//
+// FUSE < 0: the window sums go to S.  FUSE = a solve mode (n <= kFuseMaxN):
+// a row's window sums stay in LDS and one thread per output pixel computes
+// its inverse and stores the record and window means, as invert_kernel would.
+template <int R, int NG, int KW, int FUSE>
 __global__ __launch_bounds__((NG + NG * (NG + 1) / 2 + KW - 1) / KW * 64) void moments_kernel(
     const double* __restrict__ g64, int H, int W, int band_h, int strips,
-    double* __restrict__ S) {
+    double* __restrict__ S, double eps, double* __restrict__ mu_out,
+    void* __restrict__ minv_void) {
   constexpr int K = NG + NG * (NG + 1) / 2;
   constexpr int NWM = (K + KW - 1) / KW;  // waves of the block
   constexpr int SOUT = kStrip - 2 * R;
@@ -59,6 +127,8 @@ __global__ __launch_bounds__((NG + NG * (NG + 1) / 2 + KW - 1) / KW * 64) void m
   constexpr int NSPLIT = (NWM * 64) / K < 1 ? 1 : ((NWM * 64) / K > 4 ? 4 : (NWM * 64) / K);
   constexpr int JC = (SOUT + NSPLIT - 1) / NSPLIT;
   __shared__ double tr[K * TS];
+  // the fused form's window sums of one output row, [SOUT][K]
+  __shared__ double sp[FUSE >= 0 ? SOUT * K : 1];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int bid = xcd_remap(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
@@ -138,8 +208,43 @@ __global__ __launch_bounds__((NG + NG * (NG + 1) / 2 + KW - 1) / KW * 64) void m
       for (int j = 0; j < JC; ++j) {
         if (j0 + j < SOUT) {
           if (j > 0) hs += row[j + 2 * R] - row[j - 1];
-          if (x_out0 + j0 + j < W) srow[static_cast<size_t>(j) * K] = hs;
+          if (x_out0 + j0 + j < W) {
+            if constexpr (FUSE < 0) {
+              srow[static_cast<size_t>(j) * K] = hs;
+            } else {
+              sp[(j0 + j) * K + kk] = hs;
+            }
+          }
         }
+      }
+    }
+    if constexpr (FUSE >= 0) {
+      // the inverse of each output pixel of the row, from its window sums
+      constexpr int D = system_size(FUSE, NG);
+      constexpr int PD = D * (D + 1) / 2;
+      constexpr int RW = minv_stride(FUSE, NG);
+      using MT = typename std::conditional<FUSE != kSolveCov32, double, float>::type;
+      __syncthreads();
+      const int x = x_out0 + t;
+      if (t < SOUT && x < W) {
+        double mu[FUSE == kSolveRidge ? D - 1 : D];
+        double M[PD];
+        pixel_inverse<D, FUSE>(sp + t * K, static_cast<double>(window_count(x, y, W, H, R)),
+                               eps, mu, M);
+        const size_t p = static_cast<size_t>(y) * W + x;
+        MT* __restrict__ rec = static_cast<MT*>(minv_void) + p * RW;
+        constexpr int M0 = FUSE == kSolveRidge ? 0 : NG;
+        if constexpr (FUSE != kSolveRidge) {
+#pragma unroll
+          for (int i = 0; i < NG; ++i) {
+            mu_out[p * NG + i] = mu[i];
+            rec[i] = static_cast<MT>(mu[i]);
+          }
+#pragma unroll
+          for (int q = NG + PD; q < RW; ++q) rec[q] = MT(0);
+        }
+#pragma unroll
+        for (int q = 0; q < PD; ++q) rec[M0 + q] = static_cast<MT>(M[q]);
       }
     }
     __syncthreads();
@@ -209,51 +314,9 @@ __global__ __launch_bounds__(64) void invert_kernel(
   const int y = p / W;
   const int x = p - y * W;
   const double Np = static_cast<double>(window_count(x, y, W, H, R));
-  const double invN = 1.0 / Np;
-  const double* s = Ss + lane * K;
-
   double mu[NG];
-#pragma unroll
-  for (int i = 0; i < NG; ++i) mu[i] = RIDGE ? 0.0 : s[i] * invN;
-
-  // entry (i, j), i <= j, of the regularised system
-  auto A = [&](int i, int j) -> double {
-    if (!RIDGE) {
-      return fma(s[NG + packed_index(i, j, NG)], invN, -mu[i] * mu[j]) + (i == j ? eps : 0.0);
-    }
-    if (i == 0) return (j == 0) ? Np + eps : s[j - 1];
-    return s[NG + packed_index(i - 1, j - 1, NG)] + (i == j ? eps : 0.0);
-  };
-
   double M[PD];
-  M[0] = 1.0 / A(0, 0);
-#pragma unroll
-  for (int kap = 1; kap < D; ++kap) {
-    double g[D];
-    double u[D];
-#pragma unroll
-    for (int i = 0; i < kap; ++i) g[i] = A(i, kap);
-#pragma unroll
-    for (int i = 0; i < kap; ++i) {
-      double acc = 0.0;
-#pragma unroll
-      for (int j = 0; j < kap; ++j)
-        acc = fma(M[i <= j ? packed_index(i, j, D) : packed_index(j, i, D)], g[j], acc);
-      u[i] = acc;
-    }
-    double schur = A(kap, kap);
-#pragma unroll
-    for (int i = 0; i < kap; ++i) schur = fma(-g[i], u[i], schur);
-    const double inv = 1.0 / schur;
-#pragma unroll
-    for (int i = 0; i < kap; ++i) {
-      const double ui = u[i] * inv;
-#pragma unroll
-      for (int j = i; j < kap; ++j) M[packed_index(i, j, D)] = fma(ui, u[j], M[packed_index(i, j, D)]);
-      M[packed_index(i, kap, D)] = -ui;
-    }
-    M[packed_index(kap, kap, D)] = inv;
-  }
+  pixel_inverse<D, MODE>(Ss + lane * K, Np, eps, mu, M);
   __syncthreads();  // every lane has read its window sums
   MT* __restrict__ ob = reinterpret_cast<MT*>(Ss);
   MT* __restrict__ rec = ob + lane * RW;
@@ -601,18 +664,38 @@ __global__ __launch_bounds__(64) void spd_inverse_kernel(const double* __restric
 
 }  // namespace gk
 
-// a2 for one (n, radius): window sums of the K = n + n(n+1)/2 moments.
-template <int NG, int R>
-hipError_t moments_nr(const double* g64, int H, int W, int target, double* S, hipStream_t s) {
+// a2 for one (n, radius): window sums of the K = n + n(n+1)/2 moments, into
+// S (FUSE < 0) or, with the inverse fused in (FUSE = the solve mode), straight
+// to the window means and solve records.
+template <int NG, int R, int FUSE>
+hipError_t moments_nr(const double* g64, int H, int W, int target, double* S, double eps,
+                      double* mu, void* minv, hipStream_t s) {
   constexpr int K = NG + NG * (NG + 1) / 2;
   // two waves for up to 64 moments; above, eight waves of up to 27 moments
   constexpr int KW = K <= 64 ? (K + 1) / 2 : (K + 7) / 8;
   constexpr int NWM = (K + KW - 1) / KW;
   StripGrid g = strip_grid(H, W, R, 1, target);
-  hipLaunchKernelGGL((gk::moments_kernel<R, NG, KW>),
+  hipLaunchKernelGGL((gk::moments_kernel<R, NG, KW, FUSE>),
                      dim3(static_cast<unsigned>(g.strips * g.bands)), dim3(NWM * 64), 0, s, g64,
-                     H, W, g.band_h, g.strips, S);
+                     H, W, g.band_h, g.strips, S, eps, mu, minv);
   return hipGetLastError();
+}
+
+template <int NG, int R>
+hipError_t moments_r(const double* g64, int H, int W, int target, double* S, double eps,
+                     int mode, double* mu, void* minv, int* fused, hipStream_t s) {
+  if constexpr (NG <= gk::kFuseMaxN) {
+    *fused = 1;
+    switch (mode) {
+      case kSolveCov32: return moments_nr<NG, R, kSolveCov32>(g64, H, W, target, S, eps, mu, minv, s);
+      case kSolveCov64: return moments_nr<NG, R, kSolveCov64>(g64, H, W, target, S, eps, mu, minv, s);
+      case kSolveRidge: return moments_nr<NG, R, kSolveRidge>(g64, H, W, target, S, eps, mu, minv, s);
+      default: return hipErrorNotSupported;
+    }
+  } else {
+    *fused = 0;
+    return moments_nr<NG, R, -1>(g64, H, W, target, S, eps, mu, minv, s);
+  }
 }
 
 template <int D, int MODE>
@@ -630,22 +713,26 @@ hipError_t invert_dm(const double* S, int H, int W, int R, double eps, double* m
   return hipGetLastError();
 }
 
-// a2 for n guidance channels, every compiled radius.
+// a2 for n guidance channels, every compiled radius (with a3 fused in for
+// n <= kFuseMaxN, which *fused reports).
 template <int NG>
-hipError_t moments_n(const double* g64, int H, int W, int R, int target, double* S,
-                     hipStream_t s) {
+hipError_t moments_n(const double* g64, int H, int W, int R, int target, double* S, double eps,
+                     int mode, double* mu, void* minv, int* fused, hipStream_t s) {
   static_assert(kMinRadius == 0 && kMaxRadius == 9, "the radius list below");
   switch (R) {
-    case 0: return moments_nr<NG, 0>(g64, H, W, target, S, s);
-    case 1: return moments_nr<NG, 1>(g64, H, W, target, S, s);
-    case 2: return moments_nr<NG, 2>(g64, H, W, target, S, s);
-    case 3: return moments_nr<NG, 3>(g64, H, W, target, S, s);
-    case 4: return moments_nr<NG, 4>(g64, H, W, target, S, s);
-    case 5: return moments_nr<NG, 5>(g64, H, W, target, S, s);
-    case 6: return moments_nr<NG, 6>(g64, H, W, target, S, s);
-    case 7: return moments_nr<NG, 7>(g64, H, W, target, S, s);
-    case 8: return moments_nr<NG, 8>(g64, H, W, target, S, s);
-    case 9: return moments_nr<NG, 9>(g64, H, W, target, S, s);
+#define HGF_MOM(r) \
+  case r: return moments_r<NG, r>(g64, H, W, target, S, eps, mode, mu, minv, fused, s);
+    HGF_MOM(0)
+    HGF_MOM(1)
+    HGF_MOM(2)
+    HGF_MOM(3)
+    HGF_MOM(4)
+    HGF_MOM(5)
+    HGF_MOM(6)
+    HGF_MOM(7)
+    HGF_MOM(8)
+    HGF_MOM(9)
+#undef HGF_MOM
     default: return hipErrorNotSupported;
   }
 }

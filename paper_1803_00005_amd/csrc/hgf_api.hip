@@ -349,13 +349,16 @@ hgf_status run_guide(hgf_context* ctx, const Plan& pl, const float* guide, void*
                                at<float>(ws, pl.off_g32) + kGPad, at<double>(ws, pl.off_g64), s),
             "guide_synth");
   }
+  int fused = 0;
   {
     Stage st(ctx, 2, s);
     HGF_TRY(launch_moments(at<double>(ws, pl.off_g64), pl.n, pl.H, pl.W, pl.R,
-                           tuned_target(ctx, kTuneMoments, pl), at<double>(ws, pl.off_x), s),
+                           tuned_target(ctx, kTuneMoments, pl), at<double>(ws, pl.off_x),
+                           pl.eps, pl.mode, at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv),
+                           &fused, s),
             "moments");
   }
-  {
+  if (!fused) {
     Stage st(ctx, 3, s);
     HGF_TRY(launch_invert(at<double>(ws, pl.off_x), pl.n, pl.H, pl.W, pl.R, pl.eps, pl.mode,
                           at<double>(ws, pl.off_mu), at<char>(ws, pl.off_minv), s),

@@ -65,8 +65,12 @@ hipError_t launch_guide_synth(const float* I, int H, int W, const MonoTable& t,
                               const double* shift, float* g32, double* g64,
                               hipStream_t s);
 // a2: window sums of G_i and G_i G_j (i <= j), float64 [P][K], K = n + n(n+1)/2.
+// For few channels the same kernel also computes a3 (the arguments of
+// launch_invert) and sets *fused; S is then not written and launch_invert is
+// not needed.
 hipError_t launch_moments(const double* g64, int n, int H, int W, int R,
-                          int target_blocks, double* S, hipStream_t s);
+                          int target_blocks, double* S, double eps, int mode, double* mu,
+                          void* minv, int* fused, hipStream_t s);
 // a3: per-pixel window mean mu [P][n] (float64, covariance form) and the
 // per-pixel inverse by the bordering recursion of Prop. 1, computed in
 // float64 and stored as the solve mode says (SolveMode below).

@@ -226,8 +226,12 @@ def test_spd_inverse_matches_lu(D):
 
 
 @pytest.mark.parametrize("w,stats", [(CASES[1], "f32"), (CASES[2], "f32"), (CASES[2], "f64"),
-                                     (RIDGE_CASES[0], "f32")],
-                         ids=["n9", "n19", "n19_f64", "ridge_n6"])
+                                     (RIDGE_CASES[0], "f32"),
+                                     # n <= 4: the inverse computed inside the moment kernel
+                                     (CASES[0], "f32"), (CASES[0], "f64"), (RIDGE_CASES[1], "f32"),
+                                     (RIDGE_CASES[2], "f32")],
+                         ids=["n9", "n19", "n19_f64", "ridge_n6", "n3_fused", "n3_fused_f64",
+                              "ridge_n3_fused", "ridge_n1_fused"])
 def test_guide_statistics_match_oracle(ctx, w, stats):
     reg = "ridge" if w.name.startswith("ridge") else "covariance"
     say(f"guide statistics {w.name} ({reg}, {stats})")
