@@ -103,9 +103,11 @@ __device__ __forceinline__ void pixel_inverse(const double* __restrict__ s, doub
   }
 }
 
-// Channel counts whose moment kernel also computes the inverse (the inverse's
-// registers are few, so the window sums need not go through HBM).
-constexpr int kFuseMaxN = 4;
+// Channel counts whose moment kernel also computes the inverse, so that the
+// window sums need not go through HBM: up to n = 9 the inverse (at most 55
+// doubles of M) fits beside the moment sums in the registers; above, the
+// quad-spread inverse kernel takes over.
+constexpr int kFuseMaxN = 9;
 
 // The system size of a solve mode for n guidance channels.
 constexpr int system_size(int mode, int n) { return mode == kSolveRidge ? n + 1 : n; }
