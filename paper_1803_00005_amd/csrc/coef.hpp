@@ -42,7 +42,9 @@ constexpr int coef_lds_bytes(int nch) { return nch <= 10 ? 120 * 1024 : 50 * 102
 
 // Waves per block: one per channel group, rounded up to a multiple of the
 // four SIMDs of a CU from eight groups on, so that the solves (shared by all
-// waves) spread evenly over the SIMDs; the extra waves skip the box sums.
+// waves) spread evenly over the SIMDs; with at most four groups, eight waves,
+// so that the solves of few channels do not run on four waves alone.  The
+// extra waves skip the box sums.
 constexpr int coef_block_waves(int nw) { return nw >= 8 ? (nw + 3) / 4 * 4 : (nw <= 4 ? 8 : nw); }
 
 // LDS of a block besides the transposed window sums: the staged inverses of

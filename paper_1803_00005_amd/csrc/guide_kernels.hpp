@@ -28,6 +28,8 @@ namespace gk {
 // from L1).  The sums then pass through LDS, transposed to lanes = moments,
 // for the horizontal running sums and the coalesced stores of S[p][k]; the
 // output columns are split into up to four parts summed by separate threads.
+// Up to n = kFuseMaxN a row's window sums stay in LDS instead, and the kernel
+// also computes each output pixel's inverse (a3).
 
 // coef times the moments [K0, K0 + KW) of g (g_k, then g_i g_j, i <= j, in
 // the packed order) added to the running sums vs[k - K0]

@@ -13,7 +13,9 @@ namespace hgf {
 constexpr int kMaxN = 19;
 constexpr int kMaxD = 20;
 
-// State columns per strip in the strip kernels: one wavefront-width of columns.
+// State columns per strip of the moment kernel: one wavefront-width of
+// columns (the coefficient and output kernels choose theirs per channel count
+// and radius).
 constexpr int kStrip = 64;
 
 // Floats of padding before and after the planar float32 guidance [n+1][P]:
