@@ -6,6 +6,7 @@
 //
 //   g++ -std=c++17 -O1 -I<repo> tests/sched_harness.cpp -o sched_harness
 //   ./sched_harness <scenario>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -219,11 +220,85 @@ void scenario_slots() {
   CHECK(s.drain(ex) == HGF_OK);
 }
 
+// A long randomised stream: jobs of random size (some larger than the arena),
+// random launch failures and device errors, a device that is held now and
+// then.  Every queued job completes exactly once with the expected status,
+// launches follow submission order, ranges never overlap (checked by the
+// executor), the queue bound holds and the arena drains back to one range.
+void scenario_random() {
+  uint64_t state = 0x9e3779b97f4a7c15ull;
+  auto rnd = [&](uint64_t m) {
+    state = state * 6364136223846793005ull + 1442695040888963407ull;
+    return static_cast<size_t>((state >> 33) % m);
+  };
+  FakeExec ex;
+  ex.arena = 1 << 16;
+  constexpr int kMaxQueue = 8;
+  Scheduler<Payload> s(ex.arena, 4, kMaxQueue);
+  std::vector<int64_t> queued;
+  std::map<int64_t, hgf_status> expect;
+  std::map<int64_t, int> seen;
+  std::map<int64_t, int> status;
+  auto collect = [&](const std::vector<hgf_completion>& cs) {
+    for (const auto& c : cs) {
+      ++seen[c.id];
+      status[c.id] = c.status;
+    }
+  };
+  for (int it = 0; it < 4000; ++it) {
+    ex.held = rnd(8) == 0;
+    if (rnd(3) != 0) {
+      const size_t bytes = 1 + rnd(ex.arena + ex.arena / 8);
+      const size_t pending_before = s.pending().size();
+      int64_t id = -1;
+      const hgf_status r = s.submit(job(bytes, 1.0 + static_cast<double>(rnd(5))), &id);
+      if (r == HGF_OK) {
+        queued.push_back(id);
+        expect[id] = HGF_OK;
+        const size_t f = rnd(20);
+        if (f == 0) {
+          ex.fail_launch.insert(id);
+          expect[id] = HGF_E_DEVICE;
+        } else if (f == 1) {
+          ex.fail_run[id] = HGF_E_DEVICE;
+          expect[id] = HGF_E_DEVICE;
+        }
+      } else if (r == HGF_E_BUSY) {
+        CHECK(static_cast<int>(pending_before) >= kMaxQueue);
+      } else {
+        CHECK(r == HGF_E_NOMEM);
+        CHECK(hgf::sched::arena_align(bytes) > ex.arena);
+      }
+    }
+    CHECK(static_cast<int>(s.pending().size()) <= kMaxQueue);
+    CHECK(s.arena().used() <= ex.arena);
+    collect(poll_all(s, ex));
+  }
+  ex.held = false;
+  (void)s.drain(ex);
+  for (int it = 0; it < 1000 && s.done_count() > 0; ++it) collect(poll_all(s, ex));
+  CHECK(s.pending().empty() && s.running().empty());
+  CHECK(queued.size() > 100);
+  for (int64_t id : queued) {
+    CHECK(seen[id] == 1);
+    CHECK(status[id] == expect[id]);
+  }
+  CHECK(seen.size() == queued.size());
+  // launches (failed ones excluded) in submission order
+  std::vector<int64_t> ok_launch;
+  for (int64_t id : queued)
+    if (!ex.fail_launch.count(id)) ok_launch.push_back(id);
+  CHECK(ex.launched == ok_launch);
+  CHECK(ex.released == static_cast<int>(queued.size()));
+  CHECK(s.arena().used() == 0);
+  CHECK(s.arena().free_ranges() == 1);
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
   if (argc != 2) {
-    std::fprintf(stderr, "usage: %s fifo|alloc_failure|slow_device|failures|slots\n", argv[0]);
+    std::fprintf(stderr, "usage: %s fifo|alloc_failure|slow_device|failures|slots|random\n", argv[0]);
     return 2;
   }
   const std::string sc = argv[1];
@@ -232,6 +307,7 @@ int main(int argc, char** argv) {
   else if (sc == "slow_device") scenario_slow_device();
   else if (sc == "failures") scenario_failures();
   else if (sc == "slots") scenario_slots();
+  else if (sc == "random") scenario_random();
   else {
     std::fprintf(stderr, "unknown scenario %s\n", sc.c_str());
     return 2;

@@ -4,7 +4,7 @@ The scheduler (admission by device-memory budget, strict FIFO, bounded
 queue, slot choice, retirement) is host-only code shared by the HIP server;
 tests/sched_harness.cpp runs it against a simulated device: forced
 allocation failures, a slow device that fills the queue, failed launches and
-jobs that fail on the device.  Built with g++, once plainly and once with the
+jobs that fail on the device, and a long randomised stream of all of them.  Built with g++, once plainly and once with the
 address and undefined-behaviour sanitizers (host code only).
 """
 import os
@@ -15,7 +15,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "tests", "sched_harness.cpp")
-SCENARIOS = ["fifo", "alloc_failure", "slow_device", "failures", "slots"]
+SCENARIOS = ["fifo", "alloc_failure", "slow_device", "failures", "slots", "random"]
 
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
 
