@@ -570,3 +570,49 @@ def test_nan_costs_do_not_crash(ctx):
     assert np.all((lab >= 0) & (lab < w.labels))
     Z2, lab2 = gpu_filter(ctx, guide, cost, w)
     check(Z2, lab2, oracle_filter(guide, cost, w), cost, "clean call after non-finite input")
+
+
+def _random_case(k):
+    """A seeded random configuration across the compiled set: guidance
+    channels, basis and degree (n <= 19), radius 0..9, ragged sizes from one
+    pixel up, label counts around the 64-lane chunks, cost dtype, solve
+    precision and regularisation form."""
+    rng = np.random.default_rng(4000 + k)
+    m = int(rng.integers(1, 4))
+    basis = "power" if rng.random() < 0.3 else "monomial"
+    while True:
+        d = int(rng.integers(1, 7 if basis == "power" else 4))
+        n = m * d if basis == "power" else int(np.prod(range(d + 1, d + m + 1)) // np.prod(range(1, m + 1))) - 1
+        if n <= 19:
+            break
+    reg = "ridge" if rng.random() < 0.25 else "covariance"
+    cost_dtype = "f32" if reg == "ridge" else str(rng.choice(["f32", "f32", "bf16", "f16"]))
+    stats = "f32" if reg == "ridge" else str(rng.choice(["f32", "f64"]))
+    if reg == "ridge":
+        eps = 0.05
+    else:
+        eps = 1e-4 if n <= 9 else (1e-3 if n <= 14 else 1e-2)
+        if basis == "power" and d >= 4:
+            eps = 1e-2
+    w = W(f"rand{k}", height=int(rng.integers(1, 61)), width=int(rng.integers(1, 91)),
+          guide_channels=m, basis=basis, degree=d,
+          labels=int(rng.choice([1, 2, 5, 16, 33, 64, 65, 100, 130])),
+          radius=int(rng.integers(0, 10)), eps=eps, cost_dtype=cost_dtype, seed=5000 + k)
+    assert w.n == n
+    return w, reg, stats
+
+
+RANDOM = [_random_case(k) for k in range(24)]
+
+
+@pytest.mark.parametrize("case", RANDOM,
+                         ids=[f"{w.name}-n{w.n}-r{w.radius}-L{w.labels}-{w.height}x{w.width}-"
+                              f"{reg}-{w.cost_dtype}-{st}" for w, reg, st in RANDOM])
+def test_random_configurations_match_oracle(ctx, case):
+    w, reg, stats = case
+    say(f"random case {w.name}: {w.height}x{w.width} m={w.guide_channels} {w.basis} d={w.degree} "
+        f"n={w.n} L={w.labels} r={w.radius} {reg} eps={w.eps} {w.cost_dtype} {stats}")
+    guide, cost = synth.make_workload(w)
+    Z, lab = gpu_filter(ctx, guide, cost, w, reg=reg, stats_dtype=stats)
+    Zo = oracle_filter(guide, cost, w, reg=reg)
+    check(Z, lab, Zo, cost, w.name)
