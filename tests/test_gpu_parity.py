@@ -616,3 +616,35 @@ def test_random_configurations_match_oracle(ctx, case):
     Z, lab = gpu_filter(ctx, guide, cost, w, reg=reg, stats_dtype=stats)
     Zo = oracle_filter(guide, cost, w, reg=reg)
     check(Z, lab, Zo, cost, w.name)
+
+
+RANDOM_SPLIT = [(w, reg, st) for w, reg, st in RANDOM if w.labels >= 2 and w.cost_dtype == "f32"]
+
+
+@pytest.mark.parametrize("case", RANDOM_SPLIT, ids=[f"{w.name}-L{w.labels}-{reg}-{st}"
+                                                    for w, reg, st in RANDOM_SPLIT])
+def test_random_label_splits_equal_plain_path(ctx, case):
+    """The two-phase form over random label chunks returns the plain call's
+    costs and labels bit for bit (results do not depend on label chunking)."""
+    w, reg, stats = case
+    guide, cost = synth.make_workload(w)
+    Zp, labp = gpu_filter(ctx, guide, cost, w, reg=reg, stats_dtype=stats)
+    H, Wd, L = cost.shape
+    rng = np.random.default_rng(6000 + L + H)
+    cuts = sorted(set(int(c) for c in rng.integers(1, L, size=min(3, L - 1))))
+    bounds = list(zip([0] + cuts, cuts + [L]))
+    say(f"label splits {w.name}: {bounds}")
+    g = hgf.Guide(ctx, to_dev(guide), labels=L, radius=w.radius, eps=w.eps, degree=w.degree,
+                  basis=w.basis, reg=reg, stats_dtype=stats)
+    best = torch.empty((H, Wd), dtype=torch.float32, device=dev())
+    lab = torch.empty((H, Wd), dtype=torch.int32, device=dev())
+    Zc = np.empty((H, Wd, L))
+    for l0, l1 in bounds:
+        chunk = to_dev(cost[:, :, l0:l1])
+        out = torch.empty(chunk.shape, dtype=torch.float32, device=dev())
+        g.filter(chunk, l0, out=out, best=best, labels=lab)
+        torch.cuda.synchronize()
+        Zc[:, :, l0:l1] = out.cpu().numpy()
+    g.close()
+    np.testing.assert_array_equal(Zc, Zp)
+    np.testing.assert_array_equal(lab.cpu().numpy(), labp)
